@@ -1,0 +1,532 @@
+/*
+ * mgrit_oracle.c -- plain, serial, FP64 reference implementation of the
+ * method of Danieli & MacLachlan, "Multigrid Reduction in Time for non-linear
+ * hyperbolic equations" (arXiv 2104.09404).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it, through oracle/oracle.py (ctypes).
+ * It shares no code, header, table or helper with the GPU path.
+ *
+ * Everything is written the slow, obvious way: every formula is evaluated as
+ * the paper prints it, in the paper's order, with no blocking, fusion or
+ * sharing of sub-expressions between interfaces.  Build flags: -O2
+ * -ffp-contract=off (no fused multiply-add), no fast-math.
+ *
+ * Notation (paper section 2 and 3):
+ *   u_t + f(u)_x = 0 on [0,L), periodic                (sec 2, eq consLaw)
+ *   cells i = 0..Nx-1, dx = L/Nx, cell averages u_i      (sec 2.1)
+ *   A(u)_i = -(F_{i+1/2} - F_{i-1/2}) / dx               (eq spaceDisc)
+ *   WENO reconstruction of u^-_{i+1/2}, u^+_{i+1/2}      (sec 2.1.1, eq C, B, omega, D)
+ *   Lax-Friedrichs flux with global alpha_LF             (sec 2.1.2, eq LFflux, eigs)
+ *   Phi = SSPRK3 / SSPRK2 / forward Euler                (sec 2.2, eq SSPRK3/2/1)
+ *   MGRIT: F/FCF relaxation, FAS restriction, coarse     (sec 3.2, eq relaxation,
+ *   solve, ideal interpolation, V- and F-cycles           restrictionOperator, FAScorrection,
+ *                                                         restriction::rhs, restriction::u,
+ *                                                         coarseCorr, interpolation, Alg. 1,
+ *                                                         Fig. MGcycles)
+ *
+ * Readings of places where the paper is ambiguous (each one is listed in the
+ * design notes of the repository):
+ *   R1  WENO stencil r is {i-r, ..., i-r+k}: this is the convention under
+ *       which the printed c, d and B tables give a fifth-order scheme
+ *       (the text of sec 2.1.1 states {i+r-k, ..., i+r}).
+ *   R2  B_r is (k+1)x(k+1) and q is in R^(k+1) (the printed matrices are 3x3).
+ *   R3  The dissipative term of the LF flux carries a MINUS sign (with a plus
+ *       the flux is anti-diffusive; with minus, k=0, alpha=dx/dt and forward
+ *       Euler reproduce eq fineLF exactly, as sec 3.3.1 states).
+ *   R4  alpha_LF is one global maximum per evaluation of A (so per RK stage),
+ *       over all interfaces and both sides.
+ *   R5  N_T counts fine steps: nodes n = 0..N_T, dt = T/N_T, N_T/m chunks.
+ *   R6  The MGRIT initial guess is u^n = u0 for every node n.
+ *   R7  Interpolation adds g^{km+r} (the printed index g^{k+r} uses the
+ *       chunk index k where the node index km+r is meant).
+ *   R8  max() ignores NaN (C99 fmax).
+ *   R9  The FAS update evaluates t = Phi_l(u^{mi-1}) + g^{mi} once; the coarse
+ *       guess is t and the coarse rhs is t - Phi_{l+1}(u^{m(i-1)}).
+ *   R10 Stopping norm: Euclidean norm of the level-0 C-point residual over all
+ *       C-points and cells, r^{mi} = Phi_0(u^{mi-1}) + g^{mi} - u^{mi},
+ *       evaluated on the current iterate after an F-relaxation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Problem and scheme description                                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t flux;        /* 0: Burgers f(u) = u^2/2 (eq burgers); 1: linear advection f(u) = a u */
+    int32_t k;           /* WENO polynomial degree: 0 (piecewise constant) or 2 (WENO5)          */
+    int32_t stepper;     /* 1: forward Euler (eq SSPRK1), 2: SSPRK2, 3: SSPRK3                  */
+    int32_t nx;          /* number of cells N_x                                                 */
+    double  a;           /* advection speed (flux == 1)                                          */
+    double  eps;         /* WENO epsilon (sec 2.1.1: usually 1e-6)                              */
+    double  L;           /* domain length                                                        */
+    double  alpha_fixed; /* > 0: use this value as alpha_LF instead of the global maximum       */
+} orc_scheme;
+
+typedef struct {
+    int32_t nt;          /* number of fine time steps N_T                                        */
+    int32_t m;           /* coarsening factor                                                    */
+    int32_t levels;      /* number of levels (1 = serial time stepping)                          */
+    int32_t relax;       /* 0: F-relaxation, 1: FCF-relaxation                                   */
+    int32_t cycle;       /* 0: V-cycle (Alg. 1), 1: F-cycle (Fig. MGcycles)                      */
+    int32_t max_iter;    /* maximum number of cycles                                             */
+    int32_t init;        /* 0: initial iterate u^n = u0 for all n; 1: use the u passed in       */
+    int32_t coarse_guess;/* 0: eq restriction::u ; 1: plain injection u_{l+1}^i = u_l^{mi}      */
+    int32_t exact_coarse;/* 1: Phi_{l+1} := Phi_l applied m times (ideal coarse integrator)     */
+    int32_t pad_;
+    double  dt;          /* fine time step                                                       */
+    double  tol;         /* stop when ||r|| < tol; tol < 0 runs exactly max_iter cycles          */
+} orc_params;
+
+/* flux f and its (only) eigenvalue lambda = f'(u), sec 2 and eq eigs */
+static double flux_f(const orc_scheme* s, double u)
+{
+    if (s->flux == 0) return 0.5 * u * u;
+    return s->a * u;
+}
+
+static double flux_lambda(const orc_scheme* s, double u)
+{
+    if (s->flux == 0) return u;
+    return s->a;
+}
+
+static int wrap(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* WENO reconstruction, k = 2 (sec 2.1.1)                                     */
+/* ------------------------------------------------------------------------ */
+
+/* printed tables for k = 2: [c_{r,j}] = (1/6)[...], [d_r] = (1/10)[...], B_r = (1/6)[...] */
+static const double WENO_C[3][3] = {
+    {  2.0 / 6.0,  5.0 / 6.0, -1.0 / 6.0 },
+    { -1.0 / 6.0,  5.0 / 6.0,  2.0 / 6.0 },
+    {  2.0 / 6.0, -7.0 / 6.0, 11.0 / 6.0 },
+};
+static const double WENO_D[3] = { 3.0 / 10.0, 6.0 / 10.0, 1.0 / 10.0 };
+static const double WENO_B[3][3][3] = {
+    { { 20.0 / 6.0, -31.0 / 6.0,  11.0 / 6.0 },
+      { -31.0 / 6.0, 50.0 / 6.0, -19.0 / 6.0 },
+      {  11.0 / 6.0, -19.0 / 6.0,  8.0 / 6.0 } },
+    { {  8.0 / 6.0, -13.0 / 6.0,   5.0 / 6.0 },
+      { -13.0 / 6.0, 26.0 / 6.0, -13.0 / 6.0 },
+      {   5.0 / 6.0, -13.0 / 6.0,  8.0 / 6.0 } },
+    { {  8.0 / 6.0, -19.0 / 6.0,  11.0 / 6.0 },
+      { -19.0 / 6.0, 50.0 / 6.0, -31.0 / 6.0 },
+      {  11.0 / 6.0, -31.0 / 6.0, 20.0 / 6.0 } },
+};
+
+/*
+ * v[0..4] = q_{i-2}, ..., q_{i+2}.  Stencil r (reading R1) is the cells
+ * {i-r, i-r+1, i-r+2}, i.e. v[2-r], v[3-r], v[4-r].
+ * Candidate values q^{-,r}_{i+1/2}  (eq C).
+ */
+void orc_weno5_candidates(const double* v, double* p)
+{
+    for (int r = 0; r < 3; ++r) {
+        double acc = 0.0;
+        for (int j = 0; j < 3; ++j) acc += WENO_C[r][j] * v[2 - r + j];
+        p[r] = acc;
+    }
+}
+
+/* smoothness indicators beta^r_i = q^T B_r q  (eq B, reading R2) */
+void orc_weno5_beta(const double* v, double* beta)
+{
+    for (int r = 0; r < 3; ++r) {
+        const double* q = v + 2 - r;
+        double acc = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) acc += q[a] * WENO_B[r][a][b] * q[b];
+        beta[r] = acc;
+    }
+}
+
+/* q^-_{i+1/2} = sum_r omega_r q^{-,r}  with alpha_r = d_r/(eps+beta_r)^2 (eq omega) */
+double orc_weno5_left(const double* v, double eps)
+{
+    double p[3], beta[3], alpha[3];
+    orc_weno5_candidates(v, p);
+    orc_weno5_beta(v, beta);
+    double sum = 0.0;
+    for (int r = 0; r < 3; ++r) {
+        alpha[r] = WENO_D[r] / ((eps + beta[r]) * (eps + beta[r]));
+        sum += alpha[r];
+    }
+    double out = 0.0;
+    for (int r = 0; r < 3; ++r) out += (alpha[r] / sum) * p[r];
+    return out;
+}
+
+/* u^-_{i+1/2}: reconstruction in cell i at its right interface */
+static double recon_minus(const orc_scheme* s, const double* u, int i)
+{
+    int n = s->nx;
+    if (s->k == 0) return u[wrap(i, n)];
+    double v[5];
+    for (int j = 0; j < 5; ++j) v[j] = u[wrap(i - 2 + j, n)];
+    return orc_weno5_left(v, s->eps);
+}
+
+/* u^+_{i+1/2}: the mirror-image reconstruction in cell i+1 at its left interface (sec 2.1.1) */
+static double recon_plus(const orc_scheme* s, const double* u, int i)
+{
+    int n = s->nx;
+    if (s->k == 0) return u[wrap(i + 1, n)];
+    double v[5];
+    for (int j = 0; j < 5; ++j) v[j] = u[wrap(i + 3 - j, n)];
+    return orc_weno5_left(v, s->eps);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Semi-discrete operator A(u) (eq spaceDisc) with the LF flux (eq LFflux)   */
+/* ------------------------------------------------------------------------ */
+
+/* A[i] = -(F_{i+1/2} - F_{i-1/2})/dx.  Returns the alpha_LF used.  */
+double orc_spatial_operator(const orc_scheme* s, const double* u, double* A)
+{
+    int n = s->nx;
+    double dx = s->L / (double)n;
+    double* um = (double*)malloc(sizeof(double) * (size_t)n);
+    double* up = (double*)malloc(sizeof(double) * (size_t)n);
+    double* F = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        um[i] = recon_minus(s, u, i);
+        up[i] = recon_plus(s, u, i);
+    }
+    double alpha;
+    if (s->alpha_fixed > 0.0) {
+        alpha = s->alpha_fixed;
+    } else {
+        /* alpha_LF = max over interfaces and both sides of |lambda(u^pm)| (reading R4, R8) */
+        alpha = 0.0;
+        for (int i = 0; i < n; ++i) {
+            alpha = fmax(alpha, fabs(flux_lambda(s, um[i])));
+            alpha = fmax(alpha, fabs(flux_lambda(s, up[i])));
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        /* reading R3: minus sign on the dissipative term */
+        F[i] = 0.5 * (flux_f(s, up[i]) + flux_f(s, um[i])) - 0.5 * alpha * (up[i] - um[i]);
+    }
+    for (int i = 0; i < n; ++i) A[i] = -(F[i] - F[wrap(i - 1, n)]) / dx;
+    free(um);
+    free(up);
+    free(F);
+    return alpha;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time steppers Phi (sec 2.2)                                                */
+/* ------------------------------------------------------------------------ */
+
+/* out = Phi(u) for one step of size dt.  out may alias u. */
+void orc_phi(const orc_scheme* s, double dt, const double* u, double* out)
+{
+    int n = s->nx;
+    size_t bytes = sizeof(double) * (size_t)n;
+    double* u0 = (double*)malloc(bytes);
+    double* A = (double*)malloc(bytes);
+    double* u1 = (double*)malloc(bytes);
+    double* u2 = (double*)malloc(bytes);
+    memcpy(u0, u, bytes);
+    if (s->stepper == 1) {
+        /* eq SSPRK1: u^{n+1} = u^n + dt A(u^n) */
+        orc_spatial_operator(s, u0, A);
+        for (int i = 0; i < n; ++i) out[i] = u0[i] + dt * A[i];
+    } else if (s->stepper == 2) {
+        /* eq SSPRK2 */
+        orc_spatial_operator(s, u0, A);
+        for (int i = 0; i < n; ++i) u1[i] = u0[i] + dt * A[i];
+        orc_spatial_operator(s, u1, A);
+        for (int i = 0; i < n; ++i) out[i] = 0.5 * u0[i] + 0.5 * u1[i] + 0.5 * dt * A[i];
+    } else {
+        /* eq SSPRK3 */
+        orc_spatial_operator(s, u0, A);
+        for (int i = 0; i < n; ++i) u1[i] = u0[i] + dt * A[i];
+        orc_spatial_operator(s, u1, A);
+        for (int i = 0; i < n; ++i) u2[i] = 0.75 * u0[i] + 0.25 * u1[i] + 0.25 * dt * A[i];
+        orc_spatial_operator(s, u2, A);
+        for (int i = 0; i < n; ++i)
+            out[i] = (1.0 / 3.0) * u0[i] + (2.0 / 3.0) * u2[i] + (2.0 / 3.0) * dt * A[i];
+    }
+    free(u0);
+    free(A);
+    free(u1);
+    free(u2);
+}
+
+/* independent lines: out[b] = Phi(u[b]) for b < nlines (rows of length nx) */
+void orc_phi_lines(const orc_scheme* s, double dt, const double* u, double* out, int64_t nlines)
+{
+    for (int64_t b = 0; b < nlines; ++b)
+        orc_phi(s, dt, u + b * s->nx, out + b * s->nx);
+}
+
+/* serial time stepping (forward block substitution of eq monolithicSystem):
+   traj[0] = u0, traj[n+1] = Phi(traj[n]), n = 0..nt-1 */
+void orc_serial(const orc_scheme* s, double dt, int32_t nt, const double* u0, double* traj)
+{
+    int n = s->nx;
+    memcpy(traj, u0, sizeof(double) * (size_t)n);
+    for (int32_t t = 0; t < nt; ++t) orc_phi(s, dt, traj + (size_t)t * n, traj + (size_t)(t + 1) * n);
+}
+
+/* ------------------------------------------------------------------------ */
+/* MGRIT (sec 3)                                                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const orc_scheme* s;
+    const orc_params* p;
+    int L;               /* number of levels */
+    int nsteps[32];      /* N_l */
+    double* u[32];       /* u_(l): (N_l + 1) x nx  */
+    double* g[32];       /* g_(l): (N_l + 1) x nx  */
+    double* tmp;         /* one line */
+    double* tmp2;        /* one line */
+    double* res;         /* level-0 C-point residual, (N_0/m) x nx */
+} orc_mg;
+
+static double* node(double* base, int n, int nx) { return base + (size_t)n * (size_t)nx; }
+
+/* Phi_(l): the level-l integrator (coarse integrators by rediscretisation, dt_l = m^l dt,
+   sec 3.3; or, with exact_coarse, Phi_(l) = Phi_(0)^{m^l}) */
+static void phi_level(orc_mg* mg, int l, const double* in, double* out)
+{
+    const orc_scheme* s = mg->s;
+    int nx = s->nx;
+    if (mg->p->exact_coarse) {
+        long reps = 1;
+        for (int j = 0; j < l; ++j) reps *= mg->p->m;
+        memcpy(out, in, sizeof(double) * (size_t)nx);
+        for (long r = 0; r < reps; ++r) orc_phi(s, mg->p->dt, out, out);
+    } else {
+        double dtl = mg->p->dt;
+        for (int j = 0; j < l; ++j) dtl *= (double)mg->p->m;
+        orc_phi(s, dtl, in, out);
+    }
+}
+
+/* dst = Phi_(l)(src) + g^n, with g^n taken as zero at level 0 for n >= 1 (eq monolithicSystem) */
+static void step_with_rhs(orc_mg* mg, int l, const double* src, int n, double* dst)
+{
+    int nx = mg->s->nx;
+    phi_level(mg, l, src, mg->tmp);
+    const double* gn = node(mg->g[l], n, nx);
+    for (int i = 0; i < nx; ++i) dst[i] = mg->tmp[i] + gn[i];
+}
+
+/* F-relaxation (eq relaxation): within every chunk, step from its C-point over its F-points */
+static void relax_F(orc_mg* mg, int l)
+{
+    int nx = mg->s->nx, m = mg->p->m, N = mg->nsteps[l];
+    for (int c = 0; c < N / m; ++c)
+        for (int j = 1; j < m; ++j) {
+            int n = c * m + j;
+            step_with_rhs(mg, l, node(mg->u[l], n - 1, nx), n, node(mg->u[l], n, nx));
+        }
+}
+
+/* C-relaxation: every C-point n = cm, c >= 1, from the preceding F-point */
+static void relax_C(orc_mg* mg, int l)
+{
+    int nx = mg->s->nx, m = mg->p->m, N = mg->nsteps[l];
+    for (int c = 1; c <= N / m; ++c) {
+        int n = c * m;
+        step_with_rhs(mg, l, node(mg->u[l], n - 1, nx), n, node(mg->u[l], n, nx));
+    }
+}
+
+/* level-0 C-point residual of the current iterate (its F-points already relaxed), reading R10 */
+static double c_residual(orc_mg* mg)
+{
+    int nx = mg->s->nx, m = mg->p->m, N = mg->nsteps[0];
+    double sum = 0.0;
+    for (int i = 1; i <= N / m; ++i) {
+        step_with_rhs(mg, 0, node(mg->u[0], m * i - 1, nx), m * i, mg->tmp2);
+        const double* ui = node(mg->u[0], m * i, nx);
+        double* r = node(mg->res, i - 1, nx);
+        for (int x = 0; x < nx; ++x) {
+            r[x] = mg->tmp2[x] - ui[x];
+            sum += r[x] * r[x];
+        }
+    }
+    return sqrt(sum);
+}
+
+/* restriction with FAS (eq restrictionOperator, FAScorrection, restriction::rhs,
+   restriction::u), reading R9 */
+static void restrict_fas(orc_mg* mg, int l)
+{
+    int nx = mg->s->nx, m = mg->p->m, Nc = mg->nsteps[l + 1];
+    double* uf = mg->u[l];
+    double* gf = mg->g[l];
+    double* uc = mg->u[l + 1];
+    double* gc = mg->g[l + 1];
+    memcpy(node(uc, 0, nx), node(uf, 0, nx), sizeof(double) * (size_t)nx);
+    memcpy(node(gc, 0, nx), node(gf, 0, nx), sizeof(double) * (size_t)nx);
+    for (int i = 1; i <= Nc; ++i) {
+        /* t = Phi_l(u_l^{mi-1}) + g_l^{mi} */
+        step_with_rhs(mg, l, node(uf, m * i - 1, nx), m * i, mg->tmp2);
+        /* Phi_{l+1}(u_l^{m(i-1)}) */
+        phi_level(mg, l + 1, node(uf, m * (i - 1), nx), mg->tmp);
+        double* ui = node(uc, i, nx);
+        double* gi = node(gc, i, nx);
+        const double* uinj = node(uf, m * i, nx);
+        for (int x = 0; x < nx; ++x) {
+            gi[x] = mg->tmp2[x] - mg->tmp[x];
+            ui[x] = (mg->p->coarse_guess == 1) ? uinj[x] : mg->tmp2[x];
+        }
+    }
+}
+
+/* coarsest-level solve (eq coarseCorr): forward substitution with Phi_(L-1) */
+static void coarse_solve(orc_mg* mg, int l)
+{
+    int nx = mg->s->nx, N = mg->nsteps[l];
+    memcpy(node(mg->u[l], 0, nx), node(mg->g[l], 0, nx), sizeof(double) * (size_t)nx);
+    for (int n = 1; n <= N; ++n)
+        step_with_rhs(mg, l, node(mg->u[l], n - 1, nx), n, node(mg->u[l], n, nx));
+}
+
+/* ideal interpolation (eq interpolation, reading R7): inject the coarse values into
+   the C-points of level l, then F-relax level l */
+static void interpolate(orc_mg* mg, int l)
+{
+    int nx = mg->s->nx, m = mg->p->m, Nc = mg->nsteps[l + 1];
+    for (int i = 0; i <= Nc; ++i)
+        memcpy(node(mg->u[l], m * i, nx), node(mg->u[l + 1], i, nx), sizeof(double) * (size_t)nx);
+    relax_F(mg, l);
+}
+
+static void relax(orc_mg* mg, int l)
+{
+    relax_F(mg, l);
+    if (mg->p->relax == 1) {
+        relax_C(mg, l);
+        relax_F(mg, l);
+    }
+}
+
+/* V-cycle (Alg. 1) */
+static void vcycle(orc_mg* mg, int l)
+{
+    if (l == mg->L - 1) {
+        coarse_solve(mg, l);
+        return;
+    }
+    relax(mg, l);
+    restrict_fas(mg, l);
+    vcycle(mg, l + 1);
+    interpolate(mg, l);
+}
+
+/* F-cycle (Fig. MGcycles): descend with relaxation and restriction, solve on the
+   coarsest level, and on the way up run a V-cycle from every level l >= 1 before
+   interpolating to level l-1 */
+static void fcycle(orc_mg* mg, int l)
+{
+    if (l == mg->L - 1) {
+        coarse_solve(mg, l);
+        return;
+    }
+    relax(mg, l);
+    restrict_fas(mg, l);
+    fcycle(mg, l + 1);
+    interpolate(mg, l);
+    if (l > 0) vcycle(mg, l);
+}
+
+/*
+ * Multilevel FAS-MGRIT.
+ *   u0       [nx]               initial condition (g^0 of eq monolithicSystem)
+ *   u        [(nt+1) x nx]      in: initial iterate if p->init == 1; out: final iterate
+ *   res_hist [max_iter + 1]     ||r_k||, the residual of the iterate after k cycles
+ *   iters    number of cycles applied
+ * The loop: for k = 0, 1, ...: F-relax level 0 and compute r_k; stop if r_k < tol or
+ * k == max_iter; otherwise finish the cycle.  The returned iterate has had its
+ * F-points relaxed from its C-points.  Returns 0 if converged, 1 otherwise.
+ * levels == 1 is serial time stepping (the coarse solve on level 0); then
+ * res_hist[0] = 0, iters = 1.
+ */
+int orc_mgrit(const orc_scheme* s, const orc_params* p, const double* u0, double* u,
+              double* res_hist, int32_t* iters)
+{
+    orc_mg mg;
+    memset(&mg, 0, sizeof(mg));
+    mg.s = s;
+    mg.p = p;
+    mg.L = p->levels;
+    int nx = s->nx;
+    size_t line = (size_t)nx;
+    int N = p->nt;
+    for (int l = 0; l < mg.L; ++l) {
+        mg.nsteps[l] = N;
+        if (l + 1 < mg.L) N /= p->m;
+    }
+    mg.u[0] = u;
+    mg.g[0] = (double*)calloc((size_t)(p->nt + 1) * line, sizeof(double));
+    memcpy(mg.g[0], u0, sizeof(double) * line);
+    for (int l = 1; l < mg.L; ++l) {
+        mg.u[l] = (double*)calloc((size_t)(mg.nsteps[l] + 1) * line, sizeof(double));
+        mg.g[l] = (double*)calloc((size_t)(mg.nsteps[l] + 1) * line, sizeof(double));
+    }
+    mg.tmp = (double*)malloc(sizeof(double) * line);
+    mg.tmp2 = (double*)malloc(sizeof(double) * line);
+    mg.res = (double*)malloc(sizeof(double) * line * (size_t)(p->nt / p->m + 1));
+
+    /* reading R6: initial iterate */
+    if (p->init == 0)
+        for (int n = 0; n <= p->nt; ++n) memcpy(node(u, n, nx), u0, sizeof(double) * line);
+    memcpy(node(u, 0, nx), u0, sizeof(double) * line);
+
+    int status = 1;
+    if (mg.L == 1) {
+        coarse_solve(&mg, 0);
+        res_hist[0] = 0.0;
+        *iters = 1;
+        status = 0;
+    } else {
+        int k = 0;
+        for (;; ++k) {
+            relax_F(&mg, 0);
+            double r = c_residual(&mg);
+            res_hist[k] = r;
+            if (p->tol >= 0.0 && r < p->tol) {
+                status = 0;
+                break;
+            }
+            if (k == p->max_iter) break;
+            /* the rest of cycle k+1; the F-relaxation just done is its first sweep */
+            if (p->relax == 1) {
+                relax_C(&mg, 0);
+                relax_F(&mg, 0);
+            }
+            restrict_fas(&mg, 0);
+            if (p->cycle == 1) fcycle(&mg, 1);
+            else vcycle(&mg, 1);
+            interpolate(&mg, 0);
+        }
+        *iters = k;
+    }
+
+    free(mg.g[0]);
+    for (int l = 1; l < mg.L; ++l) {
+        free(mg.u[l]);
+        free(mg.g[l]);
+    }
+    free(mg.tmp);
+    free(mg.tmp2);
+    free(mg.res);
+    return status;
+}

@@ -1,0 +1,163 @@
+"""ctypes wrapper around the plain C reference implementation (``mgrit_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark import this module.  The product library never does.
+
+The shared object is compiled with gcc (``-O2 -ffp-contract=off``, no
+fast-math) into ``oracle/_build/``; :func:`build` always recompiles,
+:func:`lib` compiles only when nothing is built yet.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mgrit_oracle.c")
+BUILD_DIR = os.path.join(HERE, "_build")
+SO = os.path.join(BUILD_DIR, "libmgrit_oracle.so")
+
+_lib = None
+
+
+class Scheme(C.Structure):
+    """Mirror of ``orc_scheme`` in mgrit_oracle.c."""
+
+    _fields_ = [
+        ("flux", C.c_int32),
+        ("k", C.c_int32),
+        ("stepper", C.c_int32),
+        ("nx", C.c_int32),
+        ("a", C.c_double),
+        ("eps", C.c_double),
+        ("L", C.c_double),
+        ("alpha_fixed", C.c_double),
+    ]
+
+
+class Params(C.Structure):
+    """Mirror of ``orc_params`` in mgrit_oracle.c."""
+
+    _fields_ = [
+        ("nt", C.c_int32),
+        ("m", C.c_int32),
+        ("levels", C.c_int32),
+        ("relax", C.c_int32),
+        ("cycle", C.c_int32),
+        ("max_iter", C.c_int32),
+        ("init", C.c_int32),
+        ("coarse_guess", C.c_int32),
+        ("exact_coarse", C.c_int32),
+        ("pad_", C.c_int32),
+        ("dt", C.c_double),
+        ("tol", C.c_double),
+    ]
+
+
+def build() -> str:
+    """Compile the oracle shared object (always)."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    tmp = SO + ".tmp"
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
+           "-Wall", "-o", tmp, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SO)
+    return SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO) or os.path.getmtime(SO) < os.path.getmtime(SRC):
+            build()
+        L = C.CDLL(SO)
+        dp = C.POINTER(C.c_double)
+        L.orc_weno5_candidates.argtypes = [dp, dp]
+        L.orc_weno5_beta.argtypes = [dp, dp]
+        L.orc_weno5_left.argtypes = [dp, C.c_double]
+        L.orc_weno5_left.restype = C.c_double
+        L.orc_spatial_operator.argtypes = [C.POINTER(Scheme), dp, dp]
+        L.orc_spatial_operator.restype = C.c_double
+        L.orc_phi.argtypes = [C.POINTER(Scheme), C.c_double, dp, dp]
+        L.orc_phi_lines.argtypes = [C.POINTER(Scheme), C.c_double, dp, dp, C.c_int64]
+        L.orc_serial.argtypes = [C.POINTER(Scheme), C.c_double, C.c_int32, dp, dp]
+        L.orc_mgrit.argtypes = [C.POINTER(Scheme), C.POINTER(Params), dp, dp, dp,
+                                C.POINTER(C.c_int32)]
+        L.orc_mgrit.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def scheme(nx, flux=0, k=2, stepper=3, a=1.0, eps=1e-6, L=1.0, alpha_fixed=0.0) -> Scheme:
+    return Scheme(flux=flux, k=k, stepper=stepper, nx=nx, a=a, eps=eps, L=L,
+                  alpha_fixed=alpha_fixed)
+
+
+def params(nt, dt, m, levels, relax=0, cycle=0, max_iter=100, tol=1e-10, init=0,
+           coarse_guess=0, exact_coarse=0) -> Params:
+    return Params(nt=nt, m=m, levels=levels, relax=relax, cycle=cycle, max_iter=max_iter,
+                  init=init, coarse_guess=coarse_guess, exact_coarse=exact_coarse, pad_=0,
+                  dt=dt, tol=tol)
+
+
+def weno5_candidates(v):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_weno5_candidates(_p(v), _p(out))
+    return out
+
+
+def weno5_beta(v):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_weno5_beta(_p(v), _p(out))
+    return out
+
+
+def weno5_left(v, eps=1e-6):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    return lib().orc_weno5_left(_p(v), eps)
+
+
+def spatial_operator(s: Scheme, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    A = np.zeros_like(u)
+    alpha = lib().orc_spatial_operator(C.byref(s), _p(u), _p(A))
+    return A, alpha
+
+
+def phi(s: Scheme, dt, u):
+    """Phi applied to every row of ``u`` (shape [..., nx])."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros_like(u)
+    nlines = u.size // s.nx
+    lib().orc_phi_lines(C.byref(s), dt, _p(u), _p(out), nlines)
+    return out
+
+
+def serial(s: Scheme, dt, nt, u0):
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    traj = np.zeros((nt + 1, s.nx))
+    lib().orc_serial(C.byref(s), dt, nt, _p(u0), _p(traj))
+    return traj
+
+
+def mgrit(s: Scheme, p: Params, u0, u_init=None):
+    """Run FAS-MGRIT; returns (u [(nt+1) x nx], residual history, cycles applied, status)."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    u = np.zeros((p.nt + 1, s.nx))
+    if u_init is not None:
+        u[...] = u_init
+    hist = np.full(p.max_iter + 1, np.nan)
+    iters = C.c_int32(0)
+    st = lib().orc_mgrit(C.byref(s), C.byref(p), _p(u0), _p(u), _p(hist), C.byref(iters))
+    n = iters.value
+    return u, hist[: n + 1] if p.levels > 1 else hist[:1], n, st
