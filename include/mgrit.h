@@ -1,0 +1,243 @@
+/*
+ * mgrit.h -- C ABI of the MI355X (gfx950) MGRIT library for non-linear 1D
+ * scalar conservation laws (Danieli & MacLachlan, "Multigrid Reduction in
+ * Time for non-linear hyperbolic equations", arXiv 2104.09404).
+ *
+ * Problem (sec 2, eq consLaw): u_t + f(u)_x = 0 on [0, L), periodic, N_x
+ * cells of width dx = L/N_x holding cell averages (sec 2.1); N_T fine time
+ * steps of size dt, nodes n = 0..N_T, node 0 the initial condition.
+ *
+ * Conventions shared by every entry point
+ *   - All array pointers are DEVICE pointers to contiguous FP64 data owned by
+ *     the caller (e.g. torch tensors).  The library never allocates or frees
+ *     caller memory and allocates no device memory in any call below.
+ *   - A "line" is N_x consecutive doubles (one spatial grid function).  A
+ *     level array holds lines for nodes 0..N, node n at offset n*N_x: the
+ *     space-time iterate is stored time-major, contiguous in x.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work on that stream and returns, except where stated.
+ *   - Return codes: MGRIT_OK (0); MGRIT_NOT_CONVERGED (1, mgrit_cycle only);
+ *     MGRIT_EINVAL (-1) invalid argument, nothing enqueued; MGRIT_EHIP (-2) a
+ *     HIP runtime error; MGRIT_EUNSUPPORTED (-4) valid but not supported
+ *     (e.g. a line longer than the largest kernel configuration).  The
+ *     message of the last failure on the calling thread is returned by
+ *     mgrit_last_error().
+ *   - Arithmetic is IEEE FP64 throughout.  max() ignores NaN, so a line that
+ *     overflows (an unstable coarse integrator) never poisons alpha_LF of
+ *     another line; non-finite residual norms count as "not converged".
+ *   - Calls are not thread safe with respect to mgrit_set_profiling /
+ *     mgrit_get_profile; everything else is reentrant.
+ */
+#ifndef MGRIT_H
+#define MGRIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MGRIT_OK = 0,
+    MGRIT_NOT_CONVERGED = 1,
+    MGRIT_EINVAL = -1,
+    MGRIT_EHIP = -2,
+    MGRIT_EUNSUPPORTED = -4
+};
+
+/*
+ * The fine propagator Phi (sec 2.1 - 2.2).
+ *   flux     0: Burgers f(u) = u^2/2, lambda = u (eq burgers);
+ *            1: linear advection f(u) = a u, lambda = a.
+ *   k        WENO polynomial degree (sec 2.1.1): 0 = piecewise constant
+ *            (u^-_{i+1/2} = u_i, u^+_{i+1/2} = u_{i+1}); 2 = WENO5-JS with the
+ *            printed k = 2 tables, stencil r = {i-r, ..., i-r+2}.
+ *   stepper  1: forward Euler (eq SSPRK1); 2: SSPRK2; 3: SSPRK3 (eq SSPRK3).
+ *   nx       number of cells N_x >= 8.
+ *   a        advection speed (flux == 1).
+ *   eps      WENO epsilon of eq omega (> 0; the paper uses 1e-6).
+ *   L        domain length (> 0); dx = L/nx.
+ *   alpha_fixed  > 0: use this Lax-Friedrichs coefficient; 0: the global
+ *            alpha_LF = max over all interfaces and both sides of
+ *            |lambda(u^{+-})| of eq eigs, recomputed at every RK stage of every
+ *            line.  The LF flux is F = (f(u^-)+f(u^+))/2 - alpha (u^+ - u^-)/2
+ *            (eq LFflux with the dissipative sign that makes it the
+ *            Lax-Friedrichs scheme of eq fineLF).
+ */
+typedef struct {
+    int32_t flux;
+    int32_t k;
+    int32_t stepper;
+    int32_t nx;
+    double a;
+    double eps;
+    double L;
+    double alpha_fixed;
+} mgrit_scheme;
+
+/*
+ * MGRIT settings (sec 3.2, Alg. 1).
+ *   nt        number of fine steps N_T >= 1.
+ *   m         coarsening factor >= 2; N_T must be divisible by m^(levels-1).
+ *   levels    1..16.  Level l has N_l = N_T/m^l steps of size m^l dt; the
+ *             coarse integrators are the same scheme with that step
+ *             (rediscretisation).  levels == 1 is serial time stepping.
+ *   relax     0: F-relaxation; 1: FCF-relaxation (eq relaxation).
+ *   cycle     0: V-cycle (Alg. 1); 1: F-cycle (Fig. MGcycles).
+ *   max_iter  maximum number of cycles (>= 0).
+ *   init      0: the initial iterate is u^n = u0 at every node;
+ *             1: the caller's u is the initial iterate (resume).
+ *   coarse_guess 0: coarse initial guess of eq restriction::u;
+ *             1: plain injection.
+ *   storage   0: u holds every level-0 node, (nt+1) lines;
+ *             1: u holds the level-0 C-points only, (nt/m+1) lines.
+ *   sync_every  check convergence on the host every this many cycles
+ *             (>= 1; work enqueued after convergence is skipped on the GPU).
+ *   dt        fine step (> 0, finite).
+ *   tol       stop when the residual norm is < tol; tol < 0 runs exactly
+ *             max_iter cycles.
+ */
+typedef struct {
+    int32_t nt;
+    int32_t m;
+    int32_t levels;
+    int32_t relax;
+    int32_t cycle;
+    int32_t max_iter;
+    int32_t init;
+    int32_t coarse_guess;
+    int32_t storage;
+    int32_t sync_every;
+    double dt;
+    double tol;
+} mgrit_params;
+
+/*
+ * mgrit_phi -- one application of the fine propagator to independent lines
+ * (sec 2.2; Phi of eq monolithicSystem):  u_out[b] = Phi(u_in[b]) with step
+ * dt, for b = 0..nlines-1.  u_in, u_out: nlines x nx, may not overlap.
+ * nlines == 0 is a no-op.  Errors: EINVAL on a bad scheme, dt <= 0, a null
+ * pointer with nlines > 0, or nlines > 2^31-1.
+ */
+int mgrit_phi(const mgrit_scheme* s, double dt, const double* u_in, double* u_out,
+              int64_t nlines, void* stream);
+
+/*
+ * mgrit_serial -- serial time stepping, the forward block substitution of
+ * eq monolithicSystem: traj[0] = u0, traj[n+1] = Phi(traj[n]), n < nt.
+ * u0: nx; traj: (nt+1) x nx.  One workgroup steps the line.
+ */
+int mgrit_serial(const mgrit_scheme* s, double dt, int32_t nt, const double* u0, double* traj,
+                 void* stream);
+
+/*
+ * mgrit_relax -- relaxation on one level (eq relaxation, sec 3.2):
+ *   kind 0 (F): for every chunk c, u^{cm+j} = Phi(u^{cm+j-1}) + g^{cm+j}, j = 1..m-1;
+ *   kind 1 (C): u^{cm} = Phi(u^{cm-1}) + g^{cm}, c = 1..n/m;
+ *   kind 2 (FCF): F, then C, then F.
+ * u: (n+1) x nx level array, updated in place; g: (n+1) x nx right-hand side
+ * of the level, or NULL for g^j = 0 (level 0, j >= 1; g^0 is never read).
+ * dt is the step of this level; n % m == 0.  All chunks run concurrently.
+ */
+int mgrit_relax(const mgrit_scheme* s, double dt, int32_t m, int32_t kind, double* u,
+                const double* g, int32_t n, void* stream);
+
+/*
+ * mgrit_residual -- C-point residual and FAS restriction of one level
+ * (rows of eq monolithicSystem; eq restrictionOperator, FAScorrection,
+ * restriction::rhs, restriction::u).  For i = 1..n/m:
+ *   t_i   = Phi_l(u^{mi-1}) + g^{mi}                      (step dt)
+ *   r_i   = t_i - u^{mi}                                  -> r[i-1]      (optional)
+ *   u_c^i = t_i  (coarse_guess 0) or u^{mi} (coarse_guess 1) -> u_coarse[i] (optional)
+ *   g_c^i = t_i - Phi_{l+1}(u^{m(i-1)})                   -> g_coarse[i] (optional, step m*dt)
+ * and u_coarse[0] = u^0, g_coarse[0] = g^0 (g^0 = u^0 when g is NULL).
+ * u: (n+1) x nx with its F-points relaxed; g: as in mgrit_relax.
+ * r: (n/m) x nx; u_coarse, g_coarse: (n/m+1) x nx; each may be NULL.
+ * norm: DEVICE scalar, if non-NULL receives ||r||_2 over all C-points and
+ * cells (requires r); the sum is taken in a fixed order, so repeated calls
+ * give identical bits.  No synchronisation.
+ */
+int mgrit_residual(const mgrit_scheme* s, double dt, int32_t m, const double* u, const double* g,
+                   int32_t n, int32_t coarse_guess, double* r, double* u_coarse, double* g_coarse,
+                   double* norm, void* stream);
+
+/*
+ * mgrit_workspace_bytes -- device workspace needed by mgrit_cycle: the
+ * coarse level arrays u_l, g_l (l >= 1), a side buffer for the concurrent
+ * C-relaxation, residual partial sums and the on-device residual history.
+ * Returns 0 for invalid arguments.
+ */
+size_t mgrit_workspace_bytes(const mgrit_scheme* s, const mgrit_params* p);
+
+/*
+ * mgrit_cycle -- FAS-MGRIT iterations (sec 3.2, Alg. 1) to ||r|| < tol or
+ * max_iter cycles.  For k = 0, 1, ...: the first level-0 sweep of the next
+ * cycle F-relaxes the current iterate and yields r_k, the residual
+ * Phi_0(u^{mi-1}) - u^{mi} over all level-0 C-points; if ||r_k|| < tol or
+ * k == max_iter the iteration stops (the returned iterate then has its
+ * F-points relaxed from its C-points), otherwise the cycle is completed
+ * (restriction, coarse levels, coarsest serial solve, ideal interpolation).
+ * The level-0 F-relaxation of interpolation is left to the next cycle's
+ * first sweep (sec 3.2 notes it is redundant before pre-relaxation).
+ *   u0        nx, the initial condition (g^0 of eq monolithicSystem).
+ *   u         level-0 iterate, layout per p->storage; in/out.
+ *   workspace device scratch of at least mgrit_workspace_bytes(s, p) bytes,
+ *             256-byte aligned, owned by the caller, not shared by
+ *             concurrent calls.
+ *   res_hist  HOST array of max_iter+1 doubles: ||r_0||, ..., ||r_iters||.
+ *   iters     HOST: number of cycles applied.
+ * Synchronises the stream every p->sync_every cycles and at the end.
+ * Returns MGRIT_OK if converged, MGRIT_NOT_CONVERGED otherwise.
+ */
+int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, double* u,
+                void* workspace, size_t ws_bytes, double* res_hist, int32_t* iters, void* stream);
+
+/* message of the last failure on this thread ("" if none) */
+const char* mgrit_last_error(void);
+
+/*
+ * Kernel timing.  With profiling on, the library brackets every kernel it
+ * launches with HIP events on the launch stream and accumulates, per kernel
+ * class, the number of launches, the summed event time (ms), the number of
+ * Phi line applications and the number of cell steps (Phi applications x
+ * nx).  mgrit_get_profile synchronises the device and fills up to `cap`
+ * entries; it returns the number of classes.  mgrit_set_profiling(1) clears
+ * the counters.  Class ids: see MGRIT_KC_*.
+ */
+enum {
+    MGRIT_KC_PHI = 0,        /* mgrit_phi / mgrit_serial                        */
+    MGRIT_KC_RELAX_FC = 1,   /* fused F + C sweep (FCF first half), level 0      */
+    MGRIT_KC_RELAX_FR = 2,   /* fused F + FAS restriction sweep, level 0         */
+    MGRIT_KC_RELAX_FC_C = 3, /* fused F + C sweep, levels >= 1                   */
+    MGRIT_KC_RELAX_FR_C = 4, /* fused F + restriction sweep, levels >= 1         */
+    MGRIT_KC_INTERP = 5,     /* injection + F-relaxation (ideal interpolation)   */
+    MGRIT_KC_COARSE = 6,     /* serial solve on the coarsest level               */
+    MGRIT_KC_AUX = 7,        /* norms, copies, flags                             */
+    MGRIT_KC_COUNT = 8
+};
+
+typedef struct {
+    int64_t launches;
+    double ms;
+    double phi_lines;
+    double cell_steps;
+} mgrit_profile_entry;
+
+void mgrit_set_profiling(int on);
+int mgrit_get_profile(mgrit_profile_entry* out, int cap);
+
+/* kernel configuration chosen for a line length: cells per thread and waves
+   per line (one workgroup per line); returns MGRIT_EUNSUPPORTED if none fits */
+int mgrit_kernel_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves);
+
+/* override the configuration for line lengths nx_lo..nx_hi (used by the
+   autotuner); the pair must be compiled and cover the line.  cells_per_thread
+   == 0 clears every override.  Not thread safe. */
+int mgrit_set_kernel_config(int32_t nx_lo, int32_t nx_hi, int32_t cells_per_thread, int32_t waves);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGRIT_H */

@@ -1,0 +1,734 @@
+// api.hip -- the C ABI (include/mgrit.h): argument validation, kernel
+// configuration choice, workspace layout and the MGRIT cycle driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mgrit.h"
+#include "sweep.h"
+
+using mgk::KernelCfg;
+using mgk::SweepArgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where)
+{
+    return fail(MGRIT_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                 \
+    do {                                     \
+        hipError_t e_ = (expr);              \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// kernel configuration: smallest compiled (cells per thread, waves) whose
+// capacity 64*waves*cpt covers the line, among those that keep the WENO5 /
+// SSPRK3 kernel free of register spills
+// ---------------------------------------------------------------------------
+const KernelCfg kCfgs[] = {
+#define MGK_ENTRY(C, W) {C, W},
+    MGK_CFG_LIST(MGK_ENTRY)
+#undef MGK_ENTRY
+};
+const int kNumCfgs = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
+const int kMaxLine = 64 * 8 * 8;  // (8 cells, 8 waves): the largest spill-free WENO5 configuration
+
+struct Override {
+    int nx_lo, nx_hi;
+    KernelCfg cfg;
+};
+std::vector<Override> g_overrides;
+
+bool cfg_compiled(int cpt, int nw)
+{
+    for (int i = 0; i < kNumCfgs; ++i)
+        if (kCfgs[i].cpt == cpt && kCfgs[i].nw == nw) return true;
+    return false;
+}
+
+bool choose_cfg(int nx, KernelCfg* out)
+{
+    for (const Override& o : g_overrides)
+        if (nx >= o.nx_lo && nx <= o.nx_hi && o.cfg.cpt * o.cfg.nw * 64 >= nx) {
+            *out = o.cfg;
+            return true;
+        }
+    if (nx > kMaxLine) return false;
+    // preference order: fill one wave first, then widen to 4 cells per thread
+    // and more waves, then 8 cells per thread
+    static const KernelCfg pref[] = {{1, 1}, {2, 1}, {4, 1}, {4, 2}, {4, 4}, {4, 8}, {8, 8}};
+    for (const KernelCfg& c : pref)
+        if (c.cpt * c.nw * 64 >= nx) {
+            *out = c;
+            return true;
+        }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+int check_scheme(const mgrit_scheme* s)
+{
+    if (s == nullptr) return fail(MGRIT_EINVAL, "scheme is NULL");
+    if (s->flux != 0 && s->flux != 1) return fail(MGRIT_EINVAL, "flux must be 0 (Burgers) or 1 (advection), got %d", s->flux);
+    if (s->k != 0 && s->k != 2) return fail(MGRIT_EINVAL, "k must be 0 or 2, got %d", s->k);
+    if (s->stepper < 1 || s->stepper > 3) return fail(MGRIT_EINVAL, "stepper must be 1, 2 or 3, got %d", s->stepper);
+    if (s->nx < 8) return fail(MGRIT_EINVAL, "nx must be >= 8, got %d", s->nx);
+    if (!(s->L > 0.0) || !std::isfinite(s->L)) return fail(MGRIT_EINVAL, "L must be positive and finite");
+    if (s->k == 2 && (!(s->eps > 0.0) || !std::isfinite(s->eps))) return fail(MGRIT_EINVAL, "eps must be positive");
+    if (s->flux == 1 && !std::isfinite(s->a)) return fail(MGRIT_EINVAL, "advection speed must be finite");
+    if (!(s->alpha_fixed >= 0.0) || !std::isfinite(s->alpha_fixed)) return fail(MGRIT_EINVAL, "alpha_fixed must be >= 0");
+    KernelCfg c;
+    if (!choose_cfg(s->nx, &c))
+        return fail(MGRIT_EUNSUPPORTED, "nx = %d exceeds the largest one-workgroup line (%d cells)", s->nx, kMaxLine);
+    return MGRIT_OK;
+}
+
+int check_dt(double dt)
+{
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(MGRIT_EINVAL, "dt must be positive and finite");
+    return MGRIT_OK;
+}
+
+mgk::PhiConst phi_const(const mgrit_scheme* s)
+{
+    mgk::PhiConst pc;
+    if (s->flux == 0) {
+        pc.fa = 0.5;
+        pc.fb = 0.0;
+    } else {
+        pc.fa = 0.0;
+        pc.fb = s->a;
+    }
+    pc.two_fa = 2.0 * pc.fa;
+    pc.inv_dx = 1.0 / (s->L / (double)s->nx);
+    pc.eps = s->eps;
+    pc.alpha_fixed = s->alpha_fixed;
+    return pc;
+}
+
+SweepArgs base_args(const mgrit_scheme* s)
+{
+    SweepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = s->nx;
+    a.pc = phi_const(s);
+    return a;
+}
+
+// ---------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------
+struct PendingEvent {
+    int kc;
+    hipEvent_t e0, e1;
+    double phi_lines, cells;
+};
+bool g_prof = false;
+mgrit_profile_entry g_prof_acc[MGRIT_KC_COUNT];
+std::vector<PendingEvent> g_pending;
+
+int launch(int kc, const SweepArgs& a, const mgrit_scheme* s, hipStream_t st, double phi_lines)
+{
+    KernelCfg cfg;
+    if (!choose_cfg(s->nx, &cfg)) return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", s->nx);
+    PendingEvent pe;
+    if (g_prof) {
+        pe.kc = kc;
+        pe.phi_lines = phi_lines;
+        pe.cells = phi_lines * (double)s->nx;
+        HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
+        HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
+        HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
+    }
+    hipError_t e = mgk::launch_sweep(a, cfg, s->k, s->stepper, st);
+    if (e != hipSuccess) return hip_fail(e, "sweep kernel launch");
+    if (g_prof) {
+        HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
+        g_pending.push_back(pe);
+    }
+    return MGRIT_OK;
+}
+
+template <class F>
+int launch_aux(F&& f, hipStream_t st)
+{
+    PendingEvent pe;
+    if (g_prof) {
+        pe.kc = MGRIT_KC_AUX;
+        pe.phi_lines = 0;
+        pe.cells = 0;
+        HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
+        HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
+        HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
+    }
+    hipError_t e = f();
+    if (e != hipSuccess) return hip_fail(e, "auxiliary kernel launch");
+    if (g_prof) {
+        HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
+        g_pending.push_back(pe);
+    }
+    return MGRIT_OK;
+}
+
+int drain_profile()
+{
+    for (PendingEvent& pe : g_pending) {
+        HIP_TRY(hipEventSynchronize(pe.e1), "hipEventSynchronize");
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, pe.e0, pe.e1), "hipEventElapsedTime");
+        mgrit_profile_entry& acc = g_prof_acc[pe.kc];
+        acc.launches += 1;
+        acc.ms += ms;
+        acc.phi_lines += pe.phi_lines;
+        acc.cell_steps += pe.cells;
+        (void)hipEventDestroy(pe.e0);
+        (void)hipEventDestroy(pe.e1);
+    }
+    g_pending.clear();
+    return MGRIT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout of mgrit_cycle
+// ---------------------------------------------------------------------------
+struct Layout {
+    int L;
+    int N[16];          // steps per level
+    size_t u_off[16];   // level arrays, l >= 1 (bytes)
+    size_t g_off[16];
+    size_t side_off, partial_off, hist_off, ints_off, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_params(const mgrit_scheme* s, const mgrit_params* p)
+{
+    if (p == nullptr) return fail(MGRIT_EINVAL, "params is NULL");
+    if (p->nt < 1) return fail(MGRIT_EINVAL, "nt must be >= 1");
+    if (p->levels < 1 || p->levels > 16) return fail(MGRIT_EINVAL, "levels must be in 1..16");
+    if (p->levels > 1 && p->m < 2) return fail(MGRIT_EINVAL, "m must be >= 2");
+    if (p->relax != 0 && p->relax != 1) return fail(MGRIT_EINVAL, "relax must be 0 (F) or 1 (FCF)");
+    if (p->cycle != 0 && p->cycle != 1) return fail(MGRIT_EINVAL, "cycle must be 0 (V) or 1 (F)");
+    if (p->max_iter < 0) return fail(MGRIT_EINVAL, "max_iter must be >= 0");
+    if (p->init != 0 && p->init != 1) return fail(MGRIT_EINVAL, "init must be 0 or 1");
+    if (p->coarse_guess != 0 && p->coarse_guess != 1) return fail(MGRIT_EINVAL, "coarse_guess must be 0 or 1");
+    if (p->storage != 0 && p->storage != 1) return fail(MGRIT_EINVAL, "storage must be 0 or 1");
+    if (p->levels == 1 && p->storage != 0) return fail(MGRIT_EINVAL, "levels == 1 needs storage 0");
+    if (p->sync_every < 1) return fail(MGRIT_EINVAL, "sync_every must be >= 1");
+    if (!(p->tol == p->tol)) return fail(MGRIT_EINVAL, "tol is NaN");
+    int rc = check_dt(p->dt);
+    if (rc) return rc;
+    long long div = 1;
+    for (int l = 1; l < p->levels; ++l) {
+        div *= p->m;
+        if (div > p->nt) return fail(MGRIT_EINVAL, "m^(levels-1) exceeds nt");
+    }
+    if (p->nt % div != 0) return fail(MGRIT_EINVAL, "nt = %d is not divisible by m^(levels-1) = %lld", p->nt, div);
+    return MGRIT_OK;
+}
+
+Layout make_layout(const mgrit_scheme* s, const mgrit_params* p)
+{
+    Layout ly;
+    std::memset(&ly, 0, sizeof(ly));
+    ly.L = p->levels;
+    const size_t line = sizeof(double) * (size_t)s->nx;
+    int N = p->nt;
+    size_t off = 0;
+    for (int l = 0; l < ly.L; ++l) {
+        ly.N[l] = N;
+        if (l >= 1) {
+            ly.u_off[l] = off;
+            off = align256(off + line * (size_t)(N + 1));
+            ly.g_off[l] = off;
+            off = align256(off + line * (size_t)(N + 1));
+        }
+        if (l + 1 < ly.L) N /= p->m;
+    }
+    const int nch0 = (ly.L > 1) ? p->nt / p->m : 1;
+    ly.side_off = off;
+    off = align256(off + line * (size_t)(nch0 + 1));
+    ly.partial_off = off;
+    off = align256(off + sizeof(double) * (size_t)nch0);
+    ly.hist_off = off;
+    off = align256(off + sizeof(double) * (size_t)(p->max_iter + 2));
+    ly.ints_off = off;
+    off = align256(off + 4 * sizeof(int));
+    ly.total = off;
+    return ly;
+}
+
+// ---------------------------------------------------------------------------
+// the cycle driver
+// ---------------------------------------------------------------------------
+struct Cycle {
+    const mgrit_scheme* s;
+    const mgrit_params* p;
+    Layout ly;
+    char* ws;
+    double* u0_level;     // level-0 array (caller's u)
+    int64_t cstride0;     // lines between level-0 C-points in u
+    bool fstore0;
+    const int* flag;
+    double dtl[16];
+    hipStream_t st;
+
+    double* U(int l) { return l == 0 ? u0_level : (double*)(ws + ly.u_off[l]); }
+    double* G(int l) { return l == 0 ? nullptr : (double*)(ws + ly.g_off[l]); }
+    double* side() { return (double*)(ws + ly.side_off); }
+    double* partial() { return (double*)(ws + ly.partial_off); }
+    int64_t cstride(int l) { return l == 0 ? cstride0 : p->m; }
+    double* fout(int l) { return (l == 0 && !fstore0) ? nullptr : U(l); }
+    int kc(int l, int base0, int basec) { return l == 0 ? base0 : basec; }
+
+    // F + C-step into the side buffer (first half of FCF); residual at level 0
+    int sweep_fc(int l, bool resid)
+    {
+        SweepArgs a = base_args(s);
+        a.nchunks = ly.N[l] / p->m;
+        a.m = p->m;
+        a.nsteps = p->m - 1;
+        a.end_mode = mgk::END_CSTEP;
+        a.dt = dtl[l];
+        a.ustart = U(l);
+        a.ustart_stride = cstride(l);
+        a.fout = fout(l);
+        a.g = G(l);
+        a.side_out = side();
+        a.cref = U(l);
+        a.cref_stride = cstride(l);
+        a.resid_partial = resid ? partial() : nullptr;
+        a.flag = flag;
+        return launch(kc(l, MGRIT_KC_RELAX_FC, MGRIT_KC_RELAX_FC_C), a, s, st, (double)a.nchunks * p->m);
+    }
+
+    // F-relaxation (from the side buffer after a C-relaxation) + FAS restriction to level l+1
+    int sweep_fr(int l, bool from_side, bool resid)
+    {
+        SweepArgs a = base_args(s);
+        a.nchunks = ly.N[l] / p->m;
+        a.m = p->m;
+        a.nsteps = p->m - 1;
+        a.end_mode = mgk::END_RESTRICT;
+        a.coarse_injection = p->coarse_guess;
+        a.dt = dtl[l];
+        a.dt_next = dtl[l + 1];
+        a.ustart = U(l);
+        a.ustart_stride = cstride(l);
+        a.cref = U(l);
+        a.cref_stride = cstride(l);
+        if (from_side) {
+            // after the C-relaxation the C-points live in the side buffer; commit them
+            a.side_in = side();
+            a.ucommit = U(l);
+            a.ucommit_stride = cstride(l);
+            a.inject_last = 1;
+            a.cref = side();
+            a.cref_stride = 1;
+        }
+        a.fout = fout(l);
+        a.g = G(l);
+        a.uc_out = U(l + 1);
+        a.gc_out = G(l + 1);
+        a.resid_partial = resid ? partial() : nullptr;
+        a.flag = flag;
+        return launch(kc(l, MGRIT_KC_RELAX_FR, MGRIT_KC_RELAX_FR_C), a, s, st, (double)a.nchunks * (p->m + 1));
+    }
+
+    // ideal interpolation: inject level l+1 into the C-points of level l, then F-relax
+    int interp(int l, bool relax_f)
+    {
+        SweepArgs a = base_args(s);
+        a.nchunks = ly.N[l] / p->m;
+        a.m = p->m;
+        a.nsteps = relax_f ? p->m - 1 : 0;
+        a.end_mode = mgk::END_NONE;
+        a.inject_last = 1;
+        a.dt = dtl[l];
+        a.ustart = U(l + 1);
+        a.ustart_stride = 1;
+        a.ucommit = U(l);
+        a.ucommit_stride = cstride(l);
+        a.fout = relax_f ? fout(l) : nullptr;
+        a.g = G(l);
+        a.flag = flag;
+        return launch(MGRIT_KC_INTERP, a, s, st, (double)a.nchunks * a.nsteps);
+    }
+
+    // serial solve on level l: v^0 = g^0, v^n = Phi(v^{n-1}) + g^n
+    int coarse(int l)
+    {
+        SweepArgs a = base_args(s);
+        a.nchunks = 1;
+        a.m = 0;
+        a.nsteps = ly.N[l];
+        a.end_mode = mgk::END_NONE;
+        a.dt = dtl[l];
+        a.ustart = G(l);
+        a.ustart_stride = 0;
+        a.ucommit = U(l);
+        a.ucommit_stride = 0;
+        a.fout = U(l);
+        a.g = G(l);
+        a.flag = flag;
+        return launch(MGRIT_KC_COARSE, a, s, st, (double)ly.N[l]);
+    }
+
+    int relax(int l)  // F or FCF on level l >= 1, then restriction
+    {
+        int rc;
+        if (p->relax == 1) {
+            if ((rc = sweep_fc(l, false))) return rc;
+            return sweep_fr(l, true, false);
+        }
+        return sweep_fr(l, false, false);
+    }
+
+    int vcycle(int l)
+    {
+        int rc;
+        if (l == ly.L - 1) return coarse(l);
+        if ((rc = relax(l))) return rc;
+        if ((rc = vcycle(l + 1))) return rc;
+        return interp(l, true);
+    }
+
+    int fcycle(int l)
+    {
+        int rc;
+        if (l == ly.L - 1) return coarse(l);
+        if ((rc = relax(l))) return rc;
+        if ((rc = fcycle(l + 1))) return rc;
+        if ((rc = interp(l, true))) return rc;
+        if (l > 0) return vcycle(l);
+        return MGRIT_OK;
+    }
+};
+
+}  // namespace
+
+// ===========================================================================
+// exported C ABI
+// ===========================================================================
+extern "C" {
+
+const char* mgrit_last_error(void) { return g_err.c_str(); }
+
+void mgrit_set_profiling(int on)
+{
+    g_prof = on != 0;
+    std::memset(g_prof_acc, 0, sizeof(g_prof_acc));
+    for (PendingEvent& pe : g_pending) {
+        (void)hipEventDestroy(pe.e0);
+        (void)hipEventDestroy(pe.e1);
+    }
+    g_pending.clear();
+}
+
+int mgrit_get_profile(mgrit_profile_entry* out, int cap)
+{
+    int rc = drain_profile();
+    if (rc) return rc;
+    const int n = cap < MGRIT_KC_COUNT ? cap : MGRIT_KC_COUNT;
+    for (int i = 0; i < n; ++i) out[i] = g_prof_acc[i];
+    return MGRIT_KC_COUNT;
+}
+
+int mgrit_kernel_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves)
+{
+    KernelCfg c;
+    if (!choose_cfg(nx, &c)) return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", nx);
+    if (cells_per_thread) *cells_per_thread = c.cpt;
+    if (waves) *waves = c.nw;
+    return MGRIT_OK;
+}
+
+// Override the configuration for line lengths in [nx_lo, nx_hi] (autotuner);
+// cpt = 0 clears all overrides.
+int mgrit_set_kernel_config(int32_t nx_lo, int32_t nx_hi, int32_t cpt, int32_t waves)
+{
+    if (cpt == 0) {
+        g_overrides.clear();
+        return MGRIT_OK;
+    }
+    if (!cfg_compiled(cpt, waves)) return fail(MGRIT_EINVAL, "configuration (%d, %d) is not compiled", cpt, waves);
+    if (nx_lo > nx_hi) return fail(MGRIT_EINVAL, "empty range");
+    g_overrides.insert(g_overrides.begin(), Override{nx_lo, nx_hi, KernelCfg{cpt, waves}});
+    return MGRIT_OK;
+}
+
+int mgrit_phi(const mgrit_scheme* s, double dt, const double* u_in, double* u_out, int64_t nlines, void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if ((rc = check_dt(dt))) return rc;
+    if (nlines < 0 || nlines > 2147483647LL) return fail(MGRIT_EINVAL, "nlines out of range");
+    if (nlines == 0) return MGRIT_OK;
+    if (u_in == nullptr || u_out == nullptr) return fail(MGRIT_EINVAL, "NULL array");
+    SweepArgs a = base_args(s);
+    a.nchunks = (int)nlines;
+    a.nsteps = 0;
+    a.end_mode = mgk::END_PHI;
+    a.dt = dt;
+    a.ustart = u_in;
+    a.ustart_stride = 1;
+    a.side_out = u_out;
+    return launch(MGRIT_KC_PHI, a, s, (hipStream_t)stream, (double)nlines);
+}
+
+int mgrit_serial(const mgrit_scheme* s, double dt, int32_t nt, const double* u0, double* traj, void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if ((rc = check_dt(dt))) return rc;
+    if (nt < 0) return fail(MGRIT_EINVAL, "nt must be >= 0");
+    if (u0 == nullptr || traj == nullptr) return fail(MGRIT_EINVAL, "NULL array");
+    SweepArgs a = base_args(s);
+    a.nchunks = 1;
+    a.nsteps = nt;
+    a.end_mode = mgk::END_NONE;
+    a.dt = dt;
+    a.ustart = u0;
+    a.ucommit = traj;
+    a.fout = traj;
+    return launch(MGRIT_KC_PHI, a, s, (hipStream_t)stream, (double)nt);
+}
+
+int mgrit_relax(const mgrit_scheme* s, double dt, int32_t m, int32_t kind, double* u, const double* g, int32_t n,
+                void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if ((rc = check_dt(dt))) return rc;
+    if (m < 2) return fail(MGRIT_EINVAL, "m must be >= 2");
+    if (n < 1 || n % m != 0) return fail(MGRIT_EINVAL, "n must be a positive multiple of m");
+    if (kind < 0 || kind > 2) return fail(MGRIT_EINVAL, "kind must be 0 (F), 1 (C) or 2 (FCF)");
+    if (u == nullptr) return fail(MGRIT_EINVAL, "NULL array");
+    hipStream_t st = (hipStream_t)stream;
+    const int nch = n / m;
+    auto F = [&]() {
+        SweepArgs a = base_args(s);
+        a.nchunks = nch;
+        a.m = m;
+        a.nsteps = m - 1;
+        a.end_mode = mgk::END_NONE;
+        a.dt = dt;
+        a.ustart = u;
+        a.ustart_stride = m;
+        a.fout = u;
+        a.g = g;
+        return launch(MGRIT_KC_RELAX_FR_C, a, s, st, (double)nch * (m - 1));
+    };
+    auto Cr = [&]() {
+        // chunk c (c = 0..nch-1) steps from F-point cm+m-1 to C-point (c+1)m
+        SweepArgs a = base_args(s);
+        a.nchunks = nch;
+        a.m = m;
+        a.nsteps = 1;
+        a.end_mode = mgk::END_NONE;
+        a.dt = dt;
+        a.ustart = u + (size_t)(m - 1) * s->nx;
+        a.ustart_stride = m;
+        a.fout = u + (size_t)(m - 1) * s->nx;  // node c*m + 1 relative to the shifted base = (c+1) m
+        a.g = g ? g + (size_t)(m - 1) * s->nx : nullptr;
+        return launch(MGRIT_KC_RELAX_FC_C, a, s, st, (double)nch);
+    };
+    if (kind == 0) return F();
+    if (kind == 1) return Cr();
+    if ((rc = F())) return rc;
+    if ((rc = Cr())) return rc;
+    return F();
+}
+
+int mgrit_residual(const mgrit_scheme* s, double dt, int32_t m, const double* u, const double* g, int32_t n,
+                   int32_t coarse_guess, double* r, double* u_coarse, double* g_coarse, double* norm, void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if ((rc = check_dt(dt))) return rc;
+    if (m < 2) return fail(MGRIT_EINVAL, "m must be >= 2");
+    if (n < 1 || n % m != 0) return fail(MGRIT_EINVAL, "n must be a positive multiple of m");
+    if (u == nullptr) return fail(MGRIT_EINVAL, "NULL array");
+    if (coarse_guess != 0 && coarse_guess != 1) return fail(MGRIT_EINVAL, "coarse_guess must be 0 or 1");
+    if ((u_coarse == nullptr) != (g_coarse == nullptr))
+        return fail(MGRIT_EINVAL, "u_coarse and g_coarse must both be given or both be NULL");
+    if (norm != nullptr && r == nullptr) return fail(MGRIT_EINVAL, "norm needs r");
+    if (r == nullptr && u_coarse == nullptr) return MGRIT_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const int nch = n / m;
+    const int64_t nx = s->nx;
+    // chunk c starts at its last F-point cm+m-1 and takes the step to C-point (c+1)m
+    SweepArgs a = base_args(s);
+    a.nchunks = nch;
+    a.m = m;
+    a.nsteps = 0;
+    a.dt = dt;
+    a.dt_next = dt * (double)m;
+    a.g = g;
+    a.ustart = u + (size_t)(m - 1) * nx;
+    a.ustart_stride = m;
+    a.cref = u;
+    a.cref_stride = m;
+    a.r_out = r;
+    if (u_coarse != nullptr) {
+        a.end_mode = mgk::END_RESTRICT;
+        a.coarse_injection = coarse_guess;
+        a.uc_out = u_coarse;
+        a.gc_out = g_coarse;
+        a.ystart = u;  // Phi_{l+1} acts on the C-point u^{m(i-1)}
+        a.ystart_stride = m;
+        rc = launch(MGRIT_KC_RELAX_FR_C, a, s, st, (double)nch * 2);
+    } else {
+        a.end_mode = mgk::END_CSTEP;
+        a.side_out = nullptr;
+        rc = launch(MGRIT_KC_RELAX_FC_C, a, s, st, (double)nch);
+    }
+    if (rc) return rc;
+    if (norm != nullptr) {
+        rc = launch_aux([&] { return mgk::launch_sumsq_norm(r, (int64_t)nch * nx, norm, st); }, st);
+        if (rc) return rc;
+    }
+    return MGRIT_OK;
+}
+
+size_t mgrit_workspace_bytes(const mgrit_scheme* s, const mgrit_params* p)
+{
+    if (check_scheme(s) != MGRIT_OK || check_params(s, p) != MGRIT_OK) return 0;
+    return make_layout(s, p).total;
+}
+
+int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, double* u, void* workspace,
+                size_t ws_bytes, double* res_hist, int32_t* iters, void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if ((rc = check_params(s, p))) return rc;
+    if (u0 == nullptr || u == nullptr || workspace == nullptr) return fail(MGRIT_EINVAL, "NULL array");
+    if (res_hist == nullptr || iters == nullptr) return fail(MGRIT_EINVAL, "NULL host output");
+    if (((uintptr_t)workspace & 255) != 0) return fail(MGRIT_EINVAL, "workspace must be 256-byte aligned");
+    Cycle cy;
+    cy.s = s;
+    cy.p = p;
+    cy.ly = make_layout(s, p);
+    if (ws_bytes < cy.ly.total)
+        return fail(MGRIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, cy.ly.total);
+    cy.ws = (char*)workspace;
+    cy.u0_level = u;
+    cy.st = (hipStream_t)stream;
+    const int64_t nx = s->nx;
+    const int L = p->levels;
+    cy.cstride0 = (p->storage == 0) ? (L > 1 ? p->m : 1) : 1;
+    cy.fstore0 = p->storage == 0;
+    double dtl = p->dt;
+    for (int l = 0; l < L; ++l) {
+        cy.dtl[l] = dtl;
+        dtl *= (double)p->m;
+    }
+    int* ints = (int*)(cy.ws + cy.ly.ints_off);
+    int* flag = ints;
+    int* counter = ints + 1;
+    double* hist = (double*)(cy.ws + cy.ly.hist_off);
+    hipStream_t st = cy.st;
+
+    // initial iterate
+    const int64_t nlines0 = (p->storage == 0) ? (int64_t)p->nt + 1 : (int64_t)(p->nt / p->m) + 1;
+    if (p->init == 0) {
+        if ((rc = launch_aux([&] { return mgk::launch_broadcast(u0, u, nx, nlines0, st); }, st))) return rc;
+    } else {
+        if ((rc = launch_aux([&] { return mgk::launch_broadcast(u0, u, nx, 1, st); }, st))) return rc;
+    }
+    if ((rc = launch_aux([&] { return mgk::launch_clear_ints(ints, 4, st); }, st))) return rc;
+
+    if (L == 1) {
+        // serial time stepping: the coarse solve on level 0, from g^0 = u0
+        SweepArgs a = base_args(s);
+        a.nchunks = 1;
+        a.nsteps = p->nt;
+        a.end_mode = mgk::END_NONE;
+        a.dt = p->dt;
+        a.ustart = u0;
+        a.ucommit = u;
+        a.fout = u;
+        if ((rc = launch(MGRIT_KC_COARSE, a, s, st, (double)p->nt))) return rc;
+        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        res_hist[0] = 0.0;
+        *iters = 1;
+        return MGRIT_OK;
+    }
+
+    cy.flag = flag;
+    const int nch0 = p->nt / p->m;
+    int host_flag = 0;
+    int* pinned = nullptr;
+    HIP_TRY(hipHostMalloc((void**)&pinned, sizeof(int) * 2, hipHostMallocDefault), "hipHostMalloc");
+    int k = 0;
+    for (;; ++k) {
+        // first level-0 sweep of the next cycle: F-relaxation and the residual r_k
+        if (p->relax == 1) rc = cy.sweep_fc(0, true);
+        else rc = cy.sweep_fr(0, false, true);
+        if (rc) break;
+        rc = launch_aux([&] { return mgk::launch_reduce_norm(cy.partial(), nch0, hist, counter, flag, p->tol, st); }, st);
+        if (rc) break;
+        if (k == p->max_iter) break;
+        // rest of the cycle
+        if (p->relax == 1) {
+            if ((rc = cy.sweep_fr(0, true, false))) break;
+        }
+        if (p->cycle == 1) rc = cy.fcycle(1);
+        else rc = cy.vcycle(1);
+        if (rc) break;
+        if ((rc = cy.interp(0, false))) break;
+        if ((k + 1) % p->sync_every == 0) {
+            hipError_t e = hipMemcpyAsync(pinned, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "convergence check");
+                break;
+            }
+            host_flag = pinned[0];
+            if (host_flag) break;
+        }
+    }
+    if (rc) {
+        (void)hipHostFree(pinned);
+        return rc;
+    }
+    hipError_t e = hipMemcpyAsync(pinned, ints, sizeof(int) * 2, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipHostFree(pinned);
+        return hip_fail(e, "final readback");
+    }
+    host_flag = pinned[0];
+    const int nres = pinned[1];
+    (void)hipHostFree(pinned);
+    if (nres < 1 || nres > p->max_iter + 1) return fail(MGRIT_EHIP, "inconsistent residual counter %d", nres);
+    HIP_TRY(hipMemcpy(res_hist, hist, sizeof(double) * (size_t)nres, hipMemcpyDeviceToHost), "hipMemcpy");
+    *iters = nres - 1;
+    return host_flag ? MGRIT_OK : MGRIT_NOT_CONVERGED;
+}
+
+}  // extern "C"

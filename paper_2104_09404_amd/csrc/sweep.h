@@ -1,0 +1,87 @@
+// sweep.h -- internal interface between the C-ABI layer and the sweep kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mgk {
+
+// Constants of Phi for one scheme: f(u) = u (fa u + fb), lambda(u) = 2 fa u + fb
+// (Burgers: fa = 1/2, fb = 0; linear advection: fa = 0, fb = a).
+struct PhiConst {
+    double fa, fb, two_fa;
+    double inv_dx;
+    double eps;
+    double alpha_fixed;  // > 0 replaces the global alpha_LF
+};
+
+enum EndMode : int {
+    END_NONE = 0,      // stop after the F-steps
+    END_CSTEP = 1,     // one more step to the chunk's end C-point -> side_out[c+1]
+    END_RESTRICT = 2,  // one more step t, then FAS restriction: uc_out, gc_out
+    END_PHI = 3,       // one more step (no rhs), stored at side_out[c]
+};
+
+// One launch = nchunks workgroups, chunk c handled by workgroup c.
+// Chunk c starts from line `ustart + c*ustart_stride*nx` (or from side_in[c]
+// for c >= 1 when side_in is set), optionally commits that start value to
+// `ucommit + c*ucommit_stride*nx`, then takes `nsteps` steps
+//   x <- Phi(x) + g^{cm+j}   (g == nullptr: no right-hand side)
+// storing node cm+j at fout + (cm+j)*nx when fout is set, and finishes per end_mode.
+struct SweepArgs {
+    int nx;
+    int nchunks;
+    int m;
+    int nsteps;
+    int end_mode;
+    int inject_last;       // chunk nchunks-1 also copies ustart[nchunks] -> ucommit[nchunks]
+    int coarse_injection;  // END_RESTRICT: coarse guess by injection instead of eq restriction::u
+    int pad_;
+    double dt;
+    double dt_next;        // step of the next-coarser level (END_RESTRICT)
+    PhiConst pc;
+    const double* ustart;
+    int64_t ustart_stride;
+    const double* side_in;
+    double* ucommit;
+    int64_t ucommit_stride;
+    double* fout;
+    const double* g;
+    double* side_out;
+    const double* cref;     // current value of the chunk's end C-point: cref + (c+1)*cref_stride*nx
+    int64_t cref_stride;
+    const double* ystart;   // END_RESTRICT: source of the coarse step Phi_{l+1}; nullptr = the chunk start
+    int64_t ystart_stride;
+    double* r_out;          // residual t - u^{(c+1)m} stored at r_out + c*nx (nullable)
+    double* resid_partial;  // per-chunk sum of squared C-point residuals (nullable)
+    double* uc_out;
+    double* gc_out;
+    const int* flag;        // if non-null and *flag != 0 the launch does nothing
+};
+
+struct KernelCfg {
+    int cpt;  // cells per thread
+    int nw;   // waves per workgroup (= per line)
+};
+
+// compiled (cells per thread, waves) pairs, smallest line capacity first
+#define MGK_CFG_LIST(X) \
+    X(1, 1)             \
+    X(2, 1)             \
+    X(4, 1)             \
+    X(4, 2)             \
+    X(4, 4)             \
+    X(8, 4)             \
+    X(4, 8)             \
+    X(8, 8)
+
+inline size_t smem_bytes(int nx, int nw) { return sizeof(double) * ((size_t)nx + 2 * 64 * (size_t)nw + (size_t)nw); }
+
+hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
+hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s);
+hipError_t launch_clear_ints(int* p, int n, hipStream_t s);
+hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_t s);
+hipError_t launch_reduce_norm(const double* partial, int n, double* hist, int* counter, int* flag, double tol,
+                              hipStream_t s);
+
+}  // namespace mgk

@@ -1,0 +1,533 @@
+// sweep.hip -- gfx950 kernels for the MGRIT hot path.
+//
+// One workgroup owns one line (one time chunk at one level, or one independent
+// line) and steps it through several applications of the propagator Phi,
+// entirely on chip: every thread keeps CPT consecutive cells of the line in
+// registers, the line is mirrored into LDS once per Runge-Kutta stage so that
+// threads can read their 3-cell halo (periodic wrap by index), and the global
+// Lax-Friedrichs coefficient alpha_LF of the stage is a workgroup max
+// reduction (wave shuffles, then one LDS slot per wave).
+//
+// Per RK stage (sec 2.2) a thread:
+//   1. writes its cells to LDS, barrier;
+//   2. reads its halo and reconstructs u^-_{j+1/2} and u^+_{j-1/2} for each of
+//      its cells (sec 2.1.1; WENO5 smoothness indicators shared between the
+//      two reconstructions of a cell and between neighbouring cells), takes the
+//      local max of |lambda|, publishes its two boundary reconstructions,
+//      barrier;
+//   3. reads alpha_LF and its neighbours' boundary reconstructions, forms the
+//      LF fluxes of its CPT+1 interfaces (eq LFflux) and the stage update.
+// The interface shared by two threads is evaluated by both from the same
+// operands with the same operations, so the flux difference telescopes
+// exactly and the sum of u is conserved to round-off.
+//
+// Arithmetic is FP64 only; no MFMA (this is stencil work, not a contraction).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sweep.h"
+
+namespace mgk {
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = v + __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Geometry of one thread inside its line.
+template <int CPT, int NW>
+struct Geo {
+    int nx;
+    int t;        // thread index in the line
+    int j0;       // first cell
+    int nvalid;   // cells owned (CPT, or fewer for the last thread)
+    int left;     // thread owning the cell before j0 (periodic)
+    int right;    // thread owning the cell after the last owned one (periodic)
+    bool active;
+    int halo[6];  // line indices of window positions 0,1,2 and CPT+3..CPT+5
+
+    __device__ __forceinline__ void init(int nx_)
+    {
+        nx = nx_;
+        t = threadIdx.x;
+        const int nact = (nx + CPT - 1) / CPT;
+        active = t < nact;
+        j0 = t * CPT;
+        nvalid = active ? min(CPT, nx - j0) : 0;
+        left = (t == 0) ? nact - 1 : t - 1;
+        right = (t == nact - 1) ? 0 : t + 1;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            halo[p] = wrapi(j0 - 3 + p, nx);
+            halo[3 + p] = wrapi(j0 + CPT + p, nx);
+        }
+    }
+};
+
+// Shared-memory layout: line[nx] | bm[NT] | bp[NT] | wred[NW]
+template <int NW>
+struct Smem {
+    double* line;
+    double* bm;
+    double* bp;
+    double* wred;
+    __device__ __forceinline__ void init(double* base, int nx)
+    {
+        line = base;
+        bm = base + nx;
+        bp = bm + 64 * NW;
+        wred = bp + 64 * NW;
+    }
+};
+
+// A(V) for the thread's cells: eq spaceDisc with the LF flux (eq LFflux) and
+// either the trivial (K = 0) or the WENO5 (K = 2) reconstruction.
+template <int CPT, int NW, int K>
+__device__ __forceinline__ void op_A(const double (&V)[CPT], double (&A)[CPT], const Geo<CPT, NW>& g,
+                                     const Smem<NW>& sm, const PhiConst& pc)
+{
+    if (g.active) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+            if (q < g.nvalid) sm.line[g.j0 + q] = V[q];
+    }
+    __syncthreads();
+
+    double um[CPT], up[CPT];
+    double lmax = 0.0;
+    if (g.active) {
+        // window w[p] = cell j0 - 3 + p, p = 0..CPT+5
+        double w[CPT + 6];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) w[3 + q] = V[q];
+        if (g.nvalid < CPT) {
+            // last thread of a ragged line: positions past the end wrap around
+#pragma unroll
+            for (int q = 0; q < CPT; ++q)
+                if (q >= g.nvalid) w[3 + q] = sm.line[wrapi(g.j0 + q, g.nx)];
+        }
+        if (K == 0) {
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                um[q] = w[3 + q];
+                up[q] = w[3 + q];
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                w[p] = sm.line[g.halo[p]];
+                w[CPT + 3 + p] = sm.line[g.halo[3 + p]];
+            }
+            // Smoothness indicators in the Jiang-Shu form of the printed B_r
+            // (eq B): for the stencil ending at p (cells p-2, p-1, p)
+            //   bL[p] = 13/12 (w[p-2] - 2w[p-1] + w[p])^2 + 1/4 (w[p-2] - 4w[p-1] + 3w[p])^2,
+            // for the centred stencil (p-1, p, p+1)
+            //   bC[p] = 13/12 (w[p-1] - 2w[p] + w[p+1])^2 + 1/4 (w[p+1] - w[p-1])^2,
+            // and the stencil starting at p is bL[p+2].
+            double E[CPT + 6], bL[CPT + 6], bC[CPT + 6];
+#pragma unroll
+            for (int p = 1; p <= CPT + 4; ++p) {
+                const double d2 = fma(-2.0, w[p], w[p - 1] + w[p + 1]);
+                E[p] = (13.0 / 12.0) * d2 * d2;
+            }
+#pragma unroll
+            for (int p = 3; p <= CPT + 4; ++p) {
+                const double b = fma(3.0, w[p], fma(-4.0, w[p - 1], w[p - 2]));
+                bL[p] = fma(0.25 * b, b, E[p - 1]);
+            }
+#pragma unroll
+            for (int p = 3; p <= CPT + 2; ++p) {
+                const double d = w[p + 1] - w[p - 1];
+                bC[p] = fma(0.25 * d, d, E[p]);
+            }
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                const int p = q + 3;
+                double sL = pc.eps + bL[p];
+                double sC = pc.eps + bC[p];
+                double sR = pc.eps + bL[p + 2];
+                sL *= sL;
+                sC *= sC;
+                sR *= sR;
+                // alpha_r = d_r / s_r (eq omega); multiplying numerator and
+                // denominator of sum(alpha_r p_r)/sum(alpha_r) by sL sC sR leaves
+                // one division per reconstruction.
+                const double PLC = sL * sC, PLR = sL * sR, PCR = sC * sR;
+                // u^-_{j+1/2}: d = 3/10 (stencil j..j+2), 6/10 (centred), 1/10 (j-2..j);
+                // candidates of eq C with d_r folded in.
+                const double cR = fma(-0.05, w[p + 2], fma(0.25, w[p + 1], 0.1 * w[p]));
+                const double cC = fma(0.2, w[p + 1], fma(0.5, w[p], -0.1 * w[p - 1]));
+                const double cL = fma(11.0 / 60.0, w[p], fma(-7.0 / 60.0, w[p - 1], (2.0 / 60.0) * w[p - 2]));
+                const double nm = fma(PCR, cL, fma(PLR, cC, PLC * cR));
+                const double dm = fma(0.1, PCR, fma(0.6, PLR, 0.3 * PLC));
+                um[q] = nm / dm;
+                // u^+_{j-1/2}: mirror image, d = 1/10 (j..j+2), 6/10, 3/10 (j-2..j)
+                const double dR = fma(11.0 / 60.0, w[p], fma(-7.0 / 60.0, w[p + 1], (2.0 / 60.0) * w[p + 2]));
+                const double dC = fma(0.2, w[p - 1], fma(0.5, w[p], -0.1 * w[p + 1]));
+                const double dL = fma(-0.05, w[p - 2], fma(0.25, w[p - 1], 0.1 * w[p]));
+                const double np = fma(PCR, dL, fma(PLR, dC, PLC * dR));
+                const double dp = fma(0.3, PCR, fma(0.6, PLR, 0.1 * PLC));
+                up[q] = np / dp;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            lmax = fmax(lmax, fabs(fma(pc.two_fa, um[q], pc.fb)));
+            lmax = fmax(lmax, fabs(fma(pc.two_fa, up[q], pc.fb)));
+        }
+        double last = um[0];
+#pragma unroll
+        for (int q = 1; q < CPT; ++q)
+            if (q == g.nvalid - 1) last = um[q];
+        sm.bm[g.t] = last;
+        sm.bp[g.t] = up[0];
+    }
+    lmax = wave_max(lmax);
+    if ((threadIdx.x & 63) == 0) sm.wred[threadIdx.x >> 6] = lmax;
+    __syncthreads();
+
+    double alpha = pc.alpha_fixed;
+    if (!(alpha > 0.0)) {
+        alpha = sm.wred[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) alpha = fmax(alpha, sm.wred[w]);
+    }
+    if (g.active) {
+        const double hma = -0.5 * alpha;
+        const double uml = sm.bm[g.left];
+        const double upr = sm.bp[g.right];
+        double F[CPT + 1];
+#pragma unroll
+        for (int q = 0; q <= CPT; ++q) {
+            const double uL = (q == 0) ? uml : um[q - 1];
+            const double uR = (q == CPT) ? upr : up[q];
+            const double fL = uL * fma(pc.fa, uL, pc.fb);
+            const double fR = uR * fma(pc.fa, uR, pc.fb);
+            F[q] = fma(hma, uR - uL, 0.5 * (fR + fL));
+        }
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) A[q] = (F[q] - F[q + 1]) * pc.inv_dx;
+    }
+}
+
+// x <- Phi(x) with step dt (eq SSPRK1/2/3)
+template <int CPT, int NW, int K, int ST>
+__device__ __forceinline__ void phi(double (&x)[CPT], double dt, const Geo<CPT, NW>& g, const Smem<NW>& sm,
+                                    const PhiConst& pc)
+{
+    double A[CPT];
+    if (ST == 1) {
+        op_A<CPT, NW, K>(x, A, g, sm, pc);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) x[q] = fma(dt, A[q], x[q]);
+    } else if (ST == 2) {
+        double v[CPT];
+        op_A<CPT, NW, K>(x, A, g, sm, pc);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) v[q] = fma(dt, A[q], x[q]);
+        op_A<CPT, NW, K>(v, A, g, sm, pc);
+        const double hdt = 0.5 * dt;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) x[q] = fma(hdt, A[q], fma(0.5, v[q], 0.5 * x[q]));
+    } else {
+        double v[CPT];
+        op_A<CPT, NW, K>(x, A, g, sm, pc);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) v[q] = fma(dt, A[q], x[q]);
+        op_A<CPT, NW, K>(v, A, g, sm, pc);
+        const double qdt = 0.25 * dt;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) v[q] = fma(qdt, A[q], fma(0.25, v[q], 0.75 * x[q]));
+        op_A<CPT, NW, K>(v, A, g, sm, pc);
+        const double tdt = (2.0 / 3.0) * dt;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) x[q] = fma(tdt, A[q], fma(2.0 / 3.0, v[q], (1.0 / 3.0) * x[q]));
+    }
+}
+
+template <int CPT, int NW>
+__device__ __forceinline__ void load_line(double (&x)[CPT], const double* src, const Geo<CPT, NW>& g)
+{
+    if (g.active) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+            if (q < g.nvalid) x[q] = src[g.j0 + q];
+            else x[q] = 0.0;
+    } else {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) x[q] = 0.0;
+    }
+}
+
+template <int CPT, int NW>
+__device__ __forceinline__ void store_line(const double (&x)[CPT], double* dst, const Geo<CPT, NW>& g)
+{
+    if (g.active) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+            if (q < g.nvalid) dst[g.j0 + q] = x[q];
+    }
+}
+
+template <int CPT, int NW>
+__device__ __forceinline__ void add_line(double (&x)[CPT], const double* src, const Geo<CPT, NW>& g)
+{
+    if (g.active) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+            if (q < g.nvalid) x[q] = x[q] + src[g.j0 + q];
+    }
+}
+
+template <int CPT, int NW>
+__device__ __forceinline__ void copy_line(const double* src, double* dst, const Geo<CPT, NW>& g)
+{
+    if (g.active) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+            if (q < g.nvalid) dst[g.j0 + q] = src[g.j0 + q];
+    }
+}
+
+// sum of squares of (a - b) over the line, in a fixed order; valid in thread 0
+template <int CPT, int NW>
+__device__ __forceinline__ double line_sqdiff(const double (&a)[CPT], const double* b, const Geo<CPT, NW>& g,
+                                              const Smem<NW>& sm)
+{
+    double s = 0.0;
+    if (g.active) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+            if (q < g.nvalid) {
+                const double d = a[q] - b[g.j0 + q];
+                s = fma(d, d, s);
+            }
+    }
+    s = wave_sum(s);
+    __syncthreads();  // wred may still be read as alpha slots
+    if ((threadIdx.x & 63) == 0) sm.wred[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double tot = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < NW; ++w) tot += sm.wred[w];
+    }
+    return tot;
+}
+
+// One chunk (one line) per workgroup.  See SweepArgs for the roles.
+template <int CPT, int NW, int K, int ST>
+__global__ __launch_bounds__(64 * NW) void sweep_kernel(SweepArgs a)
+{
+    if (a.flag != nullptr && *a.flag != 0) return;
+    extern __shared__ double smem_raw[];
+    Smem<NW> sm;
+    sm.init(smem_raw, a.nx);
+    Geo<CPT, NW> g;
+    g.init(a.nx);
+    const int64_t nx = a.nx;
+    const int c = blockIdx.x;
+
+    const double* src = (a.side_in != nullptr && c > 0) ? a.side_in + (int64_t)c * nx
+                                                        : a.ustart + (int64_t)c * a.ustart_stride * nx;
+    double x[CPT];
+    load_line(x, src, g);
+    if (a.ucommit != nullptr) store_line(x, a.ucommit + (int64_t)c * a.ucommit_stride * nx, g);
+    if (a.inject_last && c == a.nchunks - 1) {
+        // the level's final C-point is committed / injected as well
+        const double* last = (a.side_in != nullptr) ? a.side_in + (int64_t)a.nchunks * nx
+                                                    : a.ustart + (int64_t)a.nchunks * a.ustart_stride * nx;
+        copy_line(last, a.ucommit + (int64_t)a.nchunks * a.ucommit_stride * nx, g);
+    }
+    // the chunk's starting C-point (the source of the coarse step of END_RESTRICT)
+    const double* cstart = (a.ystart != nullptr) ? a.ystart + (int64_t)c * a.ystart_stride * nx : src;
+    if (a.end_mode == END_RESTRICT && c == 0) {
+        // coarse node 0: u_c^0 = u^0, g_c^0 = g^0 (= u^0 at level 0)
+        copy_line(cstart, a.uc_out, g);
+        copy_line(a.g != nullptr ? a.g : cstart, a.gc_out, g);
+    }
+
+    const int64_t n0 = (int64_t)c * a.m;
+    for (int j = 1; j <= a.nsteps; ++j) {
+        phi<CPT, NW, K, ST>(x, a.dt, g, sm, a.pc);
+        if (a.g != nullptr) add_line(x, a.g + (n0 + j) * nx, g);
+        if (a.fout != nullptr) store_line(x, a.fout + (n0 + j) * nx, g);
+    }
+
+    if (a.end_mode == END_NONE) return;
+    if (a.end_mode == END_PHI) {
+        phi<CPT, NW, K, ST>(x, a.dt, g, sm, a.pc);
+        store_line(x, a.side_out + (int64_t)c * nx, g);
+        return;
+    }
+    // one more step to the chunk's end C-point n1 = (c+1) m
+    const int64_t n1 = n0 + a.m;
+    phi<CPT, NW, K, ST>(x, a.dt, g, sm, a.pc);
+    if (a.g != nullptr) add_line(x, a.g + n1 * nx, g);
+    // the current value at that C-point
+    const double* cnext = a.cref + (int64_t)(c + 1) * a.cref_stride * nx;
+    if (a.resid_partial != nullptr) {
+        const double s = line_sqdiff(x, cnext, g, sm);
+        if (threadIdx.x == 0) a.resid_partial[c] = s;
+    }
+    if (a.r_out != nullptr && g.active) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+            if (q < g.nvalid) a.r_out[(int64_t)c * nx + g.j0 + q] = x[q] - cnext[g.j0 + q];
+    }
+    if (a.end_mode == END_CSTEP) {
+        if (a.side_out != nullptr) store_line(x, a.side_out + (int64_t)(c + 1) * nx, g);
+        return;
+    }
+    // END_RESTRICT: t = x; coarse guess and FAS right-hand side
+    if (a.coarse_injection) copy_line(cnext, a.uc_out + (int64_t)(c + 1) * nx, g);
+    else store_line(x, a.uc_out + (int64_t)(c + 1) * nx, g);
+    double y[CPT];
+    load_line(y, cstart, g);
+    phi<CPT, NW, K, ST>(y, a.dt_next, g, sm, a.pc);
+    if (g.active) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) y[q] = x[q] - y[q];
+    }
+    store_line(y, a.gc_out + (int64_t)(c + 1) * nx, g);
+}
+
+// ---------------------------------------------------------------------------
+// small auxiliary kernels
+// ---------------------------------------------------------------------------
+
+// dst[b] = src for b < nlines (fill every node with the initial condition)
+__global__ void broadcast_kernel(const double* src, double* dst, int64_t nx, int64_t nlines)
+{
+    const int64_t total = nx * nlines;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i % nx];
+}
+
+// out = sqrt(sum r_i^2) in a fixed order (one workgroup)
+__global__ void sumsq_norm_kernel(const double* r, int64_t n, double* out)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s = fma(r[i], r[i], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
+__global__ void clear_ints_kernel(int* p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+// norm of the residual from per-chunk partial sums, in a fixed order; records
+// it at hist[*counter], advances the counter and raises the convergence flag
+__global__ void reduce_norm_kernel(const double* partial, int n, double* hist, int* counter, int* flag, double tol)
+{
+    if (*flag != 0) return;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double nrm = sqrt(red[0]);
+        const int k = *counter;
+        hist[k] = nrm;
+        *counter = k + 1;
+        if (tol >= 0.0 && nrm < tol) *flag = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side dispatch over the compiled configurations
+// ---------------------------------------------------------------------------
+
+template <int CPT, int NW, int K, int ST>
+static hipError_t launch_one(const SweepArgs& a, hipStream_t s)
+{
+    const size_t shmem = smem_bytes(a.nx, NW);
+    auto fn = sweep_kernel<CPT, NW, K, ST>;
+    if (shmem > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3(a.nchunks), dim3(64 * NW), shmem, s, a);
+    return hipGetLastError();
+}
+
+template <int CPT, int NW>
+static hipError_t launch_cfg(const SweepArgs& a, int k, int st, hipStream_t s)
+{
+    if (k == 0) {
+        if (st == 1) return launch_one<CPT, NW, 0, 1>(a, s);
+        if (st == 2) return launch_one<CPT, NW, 0, 2>(a, s);
+        return launch_one<CPT, NW, 0, 3>(a, s);
+    }
+    if (st == 1) return launch_one<CPT, NW, 2, 1>(a, s);
+    if (st == 2) return launch_one<CPT, NW, 2, 2>(a, s);
+    return launch_one<CPT, NW, 2, 3>(a, s);
+}
+
+hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
+{
+    if (a.nchunks <= 0) return hipSuccess;
+#define MGK_CASE(C, W) \
+    if (cfg.cpt == C && cfg.nw == W) return launch_cfg<C, W>(a, k, stepper, s);
+    MGK_CFG_LIST(MGK_CASE)
+#undef MGK_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s)
+{
+    if (nlines <= 0) return hipSuccess;
+    const int64_t total = nx * nlines;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(broadcast_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, nx, nlines);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sumsq_norm_kernel, dim3(1), dim3(256), 0, s, r, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_ints(int* p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(clear_ints_kernel, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_norm(const double* partial, int n, double* hist, int* counter, int* flag, double tol,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_norm_kernel, dim3(1), dim3(256), 0, s, partial, n, hist, counter, flag, tol);
+    return hipGetLastError();
+}
+
+}  // namespace mgk

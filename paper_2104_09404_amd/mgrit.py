@@ -1,0 +1,223 @@
+"""Python binding of ``libmgrit.so`` (include/mgrit.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Arrays are torch tensors on the GPU (float64,
+contiguous); work is enqueued on torch's current stream.  There is no CPU
+fallback: importing this module without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmgrit.so")
+
+MGRIT_OK = 0
+MGRIT_NOT_CONVERGED = 1
+MGRIT_EINVAL = -1
+MGRIT_EHIP = -2
+MGRIT_EUNSUPPORTED = -4
+
+KERNEL_CLASSES = ["phi", "relax_fc_l0", "relax_fr_l0", "relax_fc_coarse", "relax_fr_coarse", "interp",
+                  "coarse_solve", "aux"]
+
+EXPORTED = ["mgrit_phi", "mgrit_serial", "mgrit_relax", "mgrit_residual", "mgrit_workspace_bytes",
+            "mgrit_cycle", "mgrit_last_error", "mgrit_set_profiling", "mgrit_get_profile",
+            "mgrit_kernel_config", "mgrit_set_kernel_config"]
+
+
+class MgritError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("libmgrit error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Scheme(C.Structure):
+    """Mirror of ``mgrit_scheme``."""
+
+    _fields_ = [
+        ("flux", C.c_int32),
+        ("k", C.c_int32),
+        ("stepper", C.c_int32),
+        ("nx", C.c_int32),
+        ("a", C.c_double),
+        ("eps", C.c_double),
+        ("L", C.c_double),
+        ("alpha_fixed", C.c_double),
+    ]
+
+
+class Params(C.Structure):
+    """Mirror of ``mgrit_params``."""
+
+    _fields_ = [
+        ("nt", C.c_int32),
+        ("m", C.c_int32),
+        ("levels", C.c_int32),
+        ("relax", C.c_int32),
+        ("cycle", C.c_int32),
+        ("max_iter", C.c_int32),
+        ("init", C.c_int32),
+        ("coarse_guess", C.c_int32),
+        ("storage", C.c_int32),
+        ("sync_every", C.c_int32),
+        ("dt", C.c_double),
+        ("tol", C.c_double),
+    ]
+
+
+class ProfileEntry(C.Structure):
+    _fields_ = [
+        ("launches", C.c_int64),
+        ("ms", C.c_double),
+        ("phi_lines", C.c_double),
+        ("cell_steps", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libmgrit.so not found at %s: build it with "
+                          "`python -m paper_2104_09404_amd.build`" % path)
+    L = C.CDLL(path)
+    vp, dp, i32, i64 = C.c_void_p, C.c_void_p, C.c_int32, C.c_int64
+    S, P = C.POINTER(Scheme), C.POINTER(Params)
+    L.mgrit_phi.argtypes = [S, C.c_double, dp, dp, i64, vp]
+    L.mgrit_serial.argtypes = [S, C.c_double, i32, dp, dp, vp]
+    L.mgrit_relax.argtypes = [S, C.c_double, i32, i32, dp, dp, i32, vp]
+    L.mgrit_residual.argtypes = [S, C.c_double, i32, dp, dp, i32, i32, dp, dp, dp, dp, vp]
+    L.mgrit_workspace_bytes.argtypes = [S, P]
+    L.mgrit_workspace_bytes.restype = C.c_size_t
+    L.mgrit_cycle.argtypes = [S, P, dp, dp, vp, C.c_size_t, C.POINTER(C.c_double), C.POINTER(C.c_int32), vp]
+    L.mgrit_last_error.restype = C.c_char_p
+    L.mgrit_set_profiling.argtypes = [C.c_int]
+    L.mgrit_get_profile.argtypes = [C.POINTER(ProfileEntry), C.c_int]
+    L.mgrit_kernel_config.argtypes = [i32, C.POINTER(i32), C.POINTER(i32)]
+    L.mgrit_set_kernel_config.argtypes = [i32, i32, i32, i32]
+    for name in EXPORTED:
+        if name in ("mgrit_last_error", "mgrit_set_profiling", "mgrit_workspace_bytes"):
+            continue
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, allow=(MGRIT_OK,)):
+    if rc not in allow:
+        raise MgritError(rc, load().mgrit_last_error().decode())
+    return rc
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError("arrays must be contiguous float64 tensors on the GPU")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> Optional[int]:
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def scheme(nx: int, flux: int = 0, k: int = 2, stepper: int = 3, a: float = 1.0, eps: float = 1e-6,
+           L: float = 1.0, alpha_fixed: float = 0.0) -> Scheme:
+    return Scheme(flux=flux, k=k, stepper=stepper, nx=nx, a=a, eps=eps, L=L, alpha_fixed=alpha_fixed)
+
+
+def params(nt: int, dt: float, m: int, levels: int, relax: int = 1, cycle: int = 0, max_iter: int = 100,
+           tol: float = 1e-10, init: int = 0, coarse_guess: int = 0, storage: int = 0,
+           sync_every: int = 1) -> Params:
+    return Params(nt=nt, m=m, levels=levels, relax=relax, cycle=cycle, max_iter=max_iter, init=init,
+                  coarse_guess=coarse_guess, storage=storage, sync_every=sync_every, dt=dt, tol=tol)
+
+
+def scheme_from_problem(pb) -> Scheme:
+    return scheme(pb.nx, flux=pb.flux, k=pb.k, stepper=pb.stepper, a=pb.a, eps=pb.eps, L=pb.L)
+
+
+def phi(s: Scheme, dt: float, u_in, u_out, stream=None):
+    """u_out[b] = Phi(u_in[b]) for every line b."""
+    nlines = u_in.numel() // s.nx
+    _check(load().mgrit_phi(C.byref(s), dt, _ptr(u_in), _ptr(u_out), nlines, _stream(stream)))
+
+
+def serial(s: Scheme, dt: float, nt: int, u0, traj, stream=None):
+    _check(load().mgrit_serial(C.byref(s), dt, nt, _ptr(u0), _ptr(traj), _stream(stream)))
+
+
+def relax(s: Scheme, dt: float, m: int, kind: int, u, g, n: int, stream=None):
+    _check(load().mgrit_relax(C.byref(s), dt, m, kind, _ptr(u), _ptr(g), n, _stream(stream)))
+
+
+def residual(s: Scheme, dt: float, m: int, u, g, n: int, coarse_guess: int = 0, r=None, u_coarse=None,
+             g_coarse=None, norm=None, stream=None):
+    _check(load().mgrit_residual(C.byref(s), dt, m, _ptr(u), _ptr(g), n, coarse_guess, _ptr(r), _ptr(u_coarse),
+                                 _ptr(g_coarse), _ptr(norm), _stream(stream)))
+
+
+def workspace_bytes(s: Scheme, p: Params) -> int:
+    n = load().mgrit_workspace_bytes(C.byref(s), C.byref(p))
+    if n == 0:
+        # surface the validation message
+        raise MgritError(MGRIT_EINVAL, load().mgrit_last_error().decode())
+    return n
+
+
+def alloc_workspace(s: Scheme, p: Params):
+    import torch
+
+    nbytes = workspace_bytes(s, p)
+    return torch.empty((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
+
+
+def cycle(s: Scheme, p: Params, u0, u, workspace=None, stream=None):
+    """Run MGRIT; returns (status, residual history list, cycles applied)."""
+    if workspace is None:
+        workspace = alloc_workspace(s, p)
+    hist = (C.c_double * (p.max_iter + 1))()
+    iters = C.c_int32(0)
+    rc = load().mgrit_cycle(C.byref(s), C.byref(p), _ptr(u0), _ptr(u), C.c_void_p(workspace.data_ptr()),
+                            workspace.numel() * 8, hist, C.byref(iters), _stream(stream))
+    _check(rc, allow=(MGRIT_OK, MGRIT_NOT_CONVERGED))
+    n = iters.value
+    nres = 1 if p.levels == 1 else n + 1
+    return rc, [hist[i] for i in range(nres)], n
+
+
+def set_profiling(on: bool):
+    load().mgrit_set_profiling(1 if on else 0)
+
+
+def get_profile() -> dict:
+    arr = (ProfileEntry * len(KERNEL_CLASSES))()
+    n = load().mgrit_get_profile(arr, len(KERNEL_CLASSES))
+    _check(0 if n > 0 else n)
+    return {KERNEL_CLASSES[i]: dict(launches=arr[i].launches, ms=arr[i].ms, phi_lines=arr[i].phi_lines,
+                                    cell_steps=arr[i].cell_steps) for i in range(len(KERNEL_CLASSES))}
+
+
+def kernel_config(nx: int):
+    c, w = C.c_int32(0), C.c_int32(0)
+    _check(load().mgrit_kernel_config(nx, C.byref(c), C.byref(w)))
+    return c.value, w.value
+
+
+def set_kernel_config(nx_lo: int, nx_hi: int, cpt: int, waves: int):
+    _check(load().mgrit_set_kernel_config(nx_lo, nx_hi, cpt, waves))

@@ -1,0 +1,89 @@
+"""The C-ABI library loads on the CPU and exports every entry point that
+include/mgrit.h declares, with the documented struct layouts (no compute
+calls: there is no GPU here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgrit.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w\s\*]*?\b(mgrit_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2104_09404_amd import mgrit
+
+    if not os.path.exists(mgrit.LIB_PATH):
+        from paper_2104_09404_amd import build
+
+        build.build()
+    return mgrit.load()
+
+
+def test_header_declares_the_four_named_calls():
+    names = declared_functions()
+    for n in ("mgrit_phi", "mgrit_relax", "mgrit_residual", "mgrit_cycle"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2104_09404_amd import mgrit
+
+    assert sorted(mgrit.EXPORTED) == declared_functions()
+
+
+def test_struct_layouts_match_header():
+    from paper_2104_09404_amd import mgrit
+
+    # mgrit_scheme: 4 int32 + 4 double; mgrit_params: 10 int32 + 2 double
+    assert C.sizeof(mgrit.Scheme) == 48
+    assert C.sizeof(mgrit.Params) == 56
+    assert mgrit.Params.dt.offset == 40
+    assert C.sizeof(mgrit.ProfileEntry) == 32
+
+
+def test_validation_errors_without_gpu(lib):
+    """Argument checks run on the host before anything touches the device."""
+    from paper_2104_09404_amd import mgrit
+
+    bad = mgrit.scheme(4)  # nx < 8
+    rc = lib.mgrit_phi(C.byref(bad), 1e-3, None, None, 1, None)
+    assert rc == mgrit.MGRIT_EINVAL
+    assert b"nx" in lib.mgrit_last_error()
+    s = mgrit.scheme(64)
+    assert lib.mgrit_phi(C.byref(s), -1.0, None, None, 1, None) == mgrit.MGRIT_EINVAL
+    assert lib.mgrit_phi(C.byref(s), 1e-3, None, None, 0, None) == mgrit.MGRIT_OK  # empty input
+    assert lib.mgrit_phi(C.byref(s), 1e-3, None, None, 3, None) == mgrit.MGRIT_EINVAL
+    big = mgrit.scheme(1 << 20)
+    assert lib.mgrit_phi(C.byref(big), 1e-3, None, None, 1, None) == mgrit.MGRIT_EUNSUPPORTED
+    p = mgrit.params(100, 1e-3, 8, 3)  # 100 not divisible by 64
+    assert lib.mgrit_workspace_bytes(C.byref(s), C.byref(p)) == 0
+    p = mgrit.params(4096, 1e-3, 8, 3)
+    n = lib.mgrit_workspace_bytes(C.byref(s), C.byref(p))
+    # two coarse levels (513 and 65 nodes, u and g) + side buffer + partials + history
+    assert n >= 8 * 64 * (2 * 513 + 2 * 65 + 513)
+
+
+def test_kernel_config_choice(lib):
+    from paper_2104_09404_amd import mgrit
+
+    assert mgrit.kernel_config(64) == (1, 1)
+    cpt, w = mgrit.kernel_config(1024)
+    assert cpt * w * 64 >= 1024
+    cpt, w = mgrit.kernel_config(1000)
+    assert cpt * w * 64 >= 1000
+    with pytest.raises(mgrit.MgritError):
+        mgrit.kernel_config(1 << 20)
