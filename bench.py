@@ -1,0 +1,166 @@
+"""Benchmark: fine cell-steps per second of FAS-MGRIT V-cycles on one MI355X.
+
+Workload (the configuration the metric is quoted on): inviscid Burgers,
+WENO5-JS (eps = 1e-6) + Lax-Friedrichs flux + SSPRK3 at CFL 0.8, N_x = 1024,
+N_T = 4096, m = 8, 3-level FCF V-cycle, FP64, u0 = 0.5 + 4 seeded Fourier
+modes (synthetic, seed 210409404 + 1).
+
+One "step" is one MGRIT iteration: the level-0 F-relaxation that yields the
+residual, the C-relaxation and second F-sweep fused with the FAS restriction,
+the level-1 FCF relaxation and restriction, the serial coarsest solve, and the
+ideal interpolation.  The timed region runs K such iterations inside one
+mgrit_cycle call on data resident in HBM (tol < 0, so no early exit), i.e.
+K cycles plus the residual sweep of the final iterate.
+
+value = (cell steps executed by all kernels of the region) / (wall time of
+the region), where a cell step is one application of Phi to one cell.  The
+library's HIP events around every kernel (on the launch stream) give the
+per-kernel durations used for the roofline of the dominant kernel, the fused
+level-0 F + C sweep.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "WENO5-SSPRK3 fine cell-steps/s in MGRIT relax; adjoint/forward time ratio"
+# algorithmic FP64 flops per cell step of WENO5-JS + LF + SSPRK3 (three stages of
+# two reconstructions per interface, LF flux, flux difference, RK combination);
+# divisions count as one flop
+FLOPS_PER_CELL_STEP = 440.0
+PEAK_FP64 = 78.6e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="budget of the reference-oracle CPU baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(pb, budget_s):
+    """The reference oracle (plain serial C) applying Phi to W1 lines on the host:
+    one Phi step of all 512 level-0 chunk lines per repetition, repeated for about
+    ``budget_s`` seconds.  Single thread."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import numpy as np
+    import oracle
+
+    so = oracle.scheme(pb.nx, flux=pb.flux, k=pb.k, stepper=pb.stepper, a=pb.a, eps=pb.eps, L=pb.L)
+    lines = np.ascontiguousarray(np.tile(pb.u0, (64, 1)))
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        lines = oracle.phi(so, pb.dt, lines)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s:
+            break
+    cells = reps * lines.shape[0] * pb.nx
+    return {"value": cells / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d Phi steps of 64 lines x %d cells of the benchmark workload (%.1f s, 1 thread)"
+                      % (reps, pb.nx, el)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the path shards in time across GPUs "
+              "by design, but no multi-GPU run is implemented); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2104_09404_amd import mgrit
+    from paper_2104_09404_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    mgrit.load()
+    pb = W.w1_burgers_weno5()
+    s = mgrit.scheme_from_problem(pb)
+    dev = torch.device("cuda:0")
+    u0 = torch.from_numpy(pb.u0).to(dev)
+    u = torch.zeros((pb.nt + 1, pb.nx), dtype=torch.float64, device=dev)
+
+    def params(iters):
+        return mgrit.params(pb.nt, pb.dt, pb.m, pb.levels, relax=pb.relax, cycle=0, max_iter=iters,
+                            tol=-1.0, storage=0, sync_every=max(iters, 1))
+
+    ws = mgrit.alloc_workspace(s, params(max(args.steps, args.warmup)))
+    if args.warmup > 0:
+        mgrit.cycle(s, params(args.warmup), u0, u, ws)
+    torch.cuda.synchronize()
+
+    # timed region: K iterations, kernel events on
+    mgrit.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, hist, n = mgrit.cycle(s, params(args.steps), u0, u, ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = mgrit.get_profile()
+    mgrit.set_profiling(False)
+
+    cells = sum(v["cell_steps"] for v in prof.values())
+    value = cells / wall
+    dom = prof["relax_fc_l0"]
+    dom_ms = dom["ms"] / max(dom["launches"], 1)
+    dom_flops = FLOPS_PER_CELL_STEP * dom["cell_steps"] / max(dom["launches"], 1)
+    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    relax_classes = ["relax_fc_l0", "relax_fr_l0", "relax_fc_coarse", "relax_fr_coarse", "interp"]
+    relax_cells = sum(prof[c]["cell_steps"] for c in relax_classes)
+    relax_ms = sum(prof[c]["ms"] for c in relax_classes)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "burgers_weno5_nx1024: Burgers, WENO5-JS + LF + SSPRK3, CFL 0.8, N_x=1024, "
+                        "N_T=4096, m=8, 3-level FCF V-cycle, FP64",
+            "nx": pb.nx, "nt": pb.nt, "m": pb.m, "levels": pb.levels, "relax": "FCF", "cycle": "V",
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "fused level-0 F+C relaxation sweep (sweep_kernel, 512 chunks x 8 Phi steps)",
+            "achieved": achieved,
+            "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved * 1e12 / PEAK_FP64,
+            "traffic": None,
+            "flops_per_cell_step": FLOPS_PER_CELL_STEP,
+            "avg_launch_ms": dom_ms,
+        },
+        "relax_cell_steps_per_s": relax_cells / (relax_ms * 1e-3) if relax_ms > 0 else None,
+        "level0_relax_cell_steps_per_s": (prof["relax_fc_l0"]["cell_steps"] + prof["relax_fr_l0"]["cell_steps"])
+        / ((prof["relax_fc_l0"]["ms"] + prof["relax_fr_l0"]["ms"]) * 1e-3),
+        "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
+        "adjoint_forward_ratio": None,
+        "mgrit_converges": bool(np.isfinite(hist[-1]) and hist[-1] < 1e-10),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pb, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

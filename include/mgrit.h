@@ -227,14 +227,18 @@ typedef struct {
 void mgrit_set_profiling(int on);
 int mgrit_get_profile(mgrit_profile_entry* out, int cap);
 
-/* kernel configuration chosen for a line length: cells per thread and waves
-   per line (one workgroup per line); returns MGRIT_EUNSUPPORTED if none fits */
-int mgrit_kernel_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves);
+/* kernel configuration chosen for `nlines` lines of `nx` cells in one launch
+   (one workgroup per line): cells per thread and waves per line.  Launches of
+   fewer than 256 lines count as latency bound and get more threads per line.
+   Returns MGRIT_EUNSUPPORTED if no compiled configuration covers the line. */
+int mgrit_kernel_config(int32_t nx, int32_t nlines, int32_t* cells_per_thread, int32_t* waves);
 
-/* override the configuration for line lengths nx_lo..nx_hi (used by the
-   autotuner); the pair must be compiled and cover the line.  cells_per_thread
-   == 0 clears every override.  Not thread safe. */
-int mgrit_set_kernel_config(int32_t nx_lo, int32_t nx_hi, int32_t cells_per_thread, int32_t waves);
+/* override the configuration for line lengths nx_lo..nx_hi in latency-bound
+   (latency != 0) or throughput launches (used by the autotuner); the pair must
+   be compiled and cover nx_hi.  cells_per_thread == 0 clears every override.
+   Not thread safe. */
+int mgrit_set_kernel_config(int32_t nx_lo, int32_t nx_hi, int32_t latency, int32_t cells_per_thread,
+                            int32_t waves);
 
 #ifdef __cplusplus
 }

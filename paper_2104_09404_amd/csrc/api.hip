@@ -56,6 +56,7 @@ const int kMaxLine = 64 * 8 * 8;  // (8 cells, 8 waves): the largest spill-free 
 
 struct Override {
     int nx_lo, nx_hi;
+    bool latency;
     KernelCfg cfg;
 };
 std::vector<Override> g_overrides;
@@ -67,16 +68,32 @@ bool cfg_compiled(int cpt, int nw)
     return false;
 }
 
-bool choose_cfg(int nx, KernelCfg* out)
+// Lines per launch below which a launch counts as latency bound (it cannot
+// fill the 256 compute units with one workgroup per line).
+const int kLatencyLines = 256;
+
+bool choose_cfg(int nx, int nlines, KernelCfg* out)
 {
+    const bool latency = nlines < kLatencyLines;
     for (const Override& o : g_overrides)
-        if (nx >= o.nx_lo && nx <= o.nx_hi && o.cfg.cpt * o.cfg.nw * 64 >= nx) {
+        if (nx >= o.nx_lo && nx <= o.nx_hi && latency == o.latency && o.cfg.cpt * o.cfg.nw * 64 >= nx) {
             *out = o.cfg;
             return true;
         }
     if (nx > kMaxLine) return false;
-    // preference order: fill one wave first, then widen to 4 cells per thread
-    // and more waves, then 8 cells per thread
+    if (latency) {
+        // per-step latency of a single line, measured on MI355X: two cells per
+        // thread over up to 8 waves beats one cell per thread over 16 waves
+        static const KernelCfg pref[] = {{1, 1}, {1, 2}, {2, 2}, {2, 4}, {2, 8}, {4, 8}, {8, 8}};
+        for (const KernelCfg& c : pref)
+            if (c.cpt * c.nw * 64 >= nx) {
+                *out = c;
+                return true;
+            }
+        return false;
+    }
+    // throughput: fill one wave first, then widen to 4 cells per thread and
+    // more waves, then 8 cells per thread
     static const KernelCfg pref[] = {{1, 1}, {2, 1}, {4, 1}, {4, 2}, {4, 4}, {4, 8}, {8, 8}};
     for (const KernelCfg& c : pref)
         if (c.cpt * c.nw * 64 >= nx) {
@@ -101,7 +118,7 @@ int check_scheme(const mgrit_scheme* s)
     if (s->flux == 1 && !std::isfinite(s->a)) return fail(MGRIT_EINVAL, "advection speed must be finite");
     if (!(s->alpha_fixed >= 0.0) || !std::isfinite(s->alpha_fixed)) return fail(MGRIT_EINVAL, "alpha_fixed must be >= 0");
     KernelCfg c;
-    if (!choose_cfg(s->nx, &c))
+    if (!choose_cfg(s->nx, kLatencyLines, &c))
         return fail(MGRIT_EUNSUPPORTED, "nx = %d exceeds the largest one-workgroup line (%d cells)", s->nx, kMaxLine);
     return MGRIT_OK;
 }
@@ -122,8 +139,7 @@ mgk::PhiConst phi_const(const mgrit_scheme* s)
         pc.fa = 0.0;
         pc.fb = s->a;
     }
-    pc.two_fa = 2.0 * pc.fa;
-    pc.inv_dx = 1.0 / (s->L / (double)s->nx);
+    pc.half_inv_dx = 0.5 / (s->L / (double)s->nx);
     pc.eps = s->eps;
     pc.alpha_fixed = s->alpha_fixed;
     return pc;
@@ -153,7 +169,8 @@ std::vector<PendingEvent> g_pending;
 int launch(int kc, const SweepArgs& a, const mgrit_scheme* s, hipStream_t st, double phi_lines)
 {
     KernelCfg cfg;
-    if (!choose_cfg(s->nx, &cfg)) return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", s->nx);
+    if (!choose_cfg(s->nx, a.nchunks, &cfg))
+        return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", s->nx);
     PendingEvent pe;
     if (g_prof) {
         pe.kc = kc;
@@ -457,18 +474,16 @@ int mgrit_get_profile(mgrit_profile_entry* out, int cap)
     return MGRIT_KC_COUNT;
 }
 
-int mgrit_kernel_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves)
+int mgrit_kernel_config(int32_t nx, int32_t nlines, int32_t* cells_per_thread, int32_t* waves)
 {
     KernelCfg c;
-    if (!choose_cfg(nx, &c)) return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", nx);
+    if (!choose_cfg(nx, nlines, &c)) return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", nx);
     if (cells_per_thread) *cells_per_thread = c.cpt;
     if (waves) *waves = c.nw;
     return MGRIT_OK;
 }
 
-// Override the configuration for line lengths in [nx_lo, nx_hi] (autotuner);
-// cpt = 0 clears all overrides.
-int mgrit_set_kernel_config(int32_t nx_lo, int32_t nx_hi, int32_t cpt, int32_t waves)
+int mgrit_set_kernel_config(int32_t nx_lo, int32_t nx_hi, int32_t latency, int32_t cpt, int32_t waves)
 {
     if (cpt == 0) {
         g_overrides.clear();
@@ -476,7 +491,8 @@ int mgrit_set_kernel_config(int32_t nx_lo, int32_t nx_hi, int32_t cpt, int32_t w
     }
     if (!cfg_compiled(cpt, waves)) return fail(MGRIT_EINVAL, "configuration (%d, %d) is not compiled", cpt, waves);
     if (nx_lo > nx_hi) return fail(MGRIT_EINVAL, "empty range");
-    g_overrides.insert(g_overrides.begin(), Override{nx_lo, nx_hi, KernelCfg{cpt, waves}});
+    if (cpt * waves * 64 < nx_hi) return fail(MGRIT_EINVAL, "configuration (%d, %d) does not cover nx = %d", cpt, waves, nx_hi);
+    g_overrides.insert(g_overrides.begin(), Override{nx_lo, nx_hi, latency != 0, KernelCfg{cpt, waves}});
     return MGRIT_OK;
 }
 

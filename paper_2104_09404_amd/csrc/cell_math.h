@@ -1,0 +1,116 @@
+// cell_math.h -- per-cell arithmetic of the sweep kernels (WENO5 reconstruction
+// and Lax-Friedrichs flux), written once and compiled for the GPU by the
+// kernels and for the host by the CPU test of the kernel arithmetic.
+#pragma once
+#include <math.h>
+
+#ifdef __HIPCC__
+#define MGK_HD __host__ __device__ __forceinline__
+#else
+#define MGK_HD inline
+#endif
+
+namespace mgk {
+
+// 13/12 (a - 2b + c)^2 + eps: the second-difference part of the smoothness
+// indicator of the stencil centred on b (shared by neighbouring cells), with
+// the eps of eq omega folded in
+MGK_HD double weno5_e(double a, double b, double c, double eps)
+{
+    const double d2 = fma(-2.0, b, a + c);
+    return fma((13.0 / 12.0) * d2, d2, eps);
+}
+
+// 1/x for x > 0 in the normal range: hardware reciprocal estimate refined by
+// two Newton steps (the host build of this header starts from 1/x itself)
+MGK_HD double recip(double x)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    double r = __builtin_amdgcn_rcp(x);
+#else
+    double r = 1.0 / x;
+#endif
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// WENO5-JS reconstructions of cell p from its window w0..w4 = u_{p-2}..u_{p+2}
+// (sec 2.1.1, eq C, B, omega, D; stencil r = cells {p-r, ..., p-r+2}):
+//   um = u^-_{p+1/2} (right face), up = u^+_{p-1/2} (left face, mirror image).
+// Em, E0, Ep are weno5_e centred on p-1, p, p+1 (eps included).
+//
+// Smoothness indicators in the Jiang-Shu form of the printed B_r (the integral
+// is over the reconstruction cell p, so the first-derivative term depends on
+// where p sits in the stencil):
+//   bL (cells p-2..p)   = 13/12 D2_{p-1}^2 + ((w0 - 4 w1 + 3 w2)/2)^2
+//   bC (cells p-1..p+1) = 13/12 D2_p^2     + ((w3 - w1)/2)^2
+//   bR (cells p..p+2)   = 13/12 D2_{p+1}^2 + ((3 w2 - 4 w3 + w4)/2)^2
+// The mirror image reconstructs from the same three cell sets, so both faces
+// share bL, bC, bR.  With s_r = (eps + b_r)^2, alpha_r = d_r / s_r; multiplying
+// the numerator and denominator of sum(alpha_r q_r) / sum(alpha_r) by
+// sL sC sR removes the divisions by s_r, and both faces share one reciprocal
+// of the product of their denominators.  Linear weights: u^- takes 3/10 on
+// cells p..p+2, 6/10 centred, 1/10 on p-2..p; u^+ the mirror (1/10, 6/10,
+// 3/10).  The candidate values of eq C carry their linear weight d_r and the
+// 1/6 of the printed c table.
+MGK_HD void weno5_cell(double w0, double w1, double w2, double w3, double w4, double Em, double E0, double Ep,
+                       double& um, double& up)
+{
+    const double b = fma(1.5, w2, fma(-2.0, w1, 0.5 * w0));
+    const double d = 0.5 * (w3 - w1);
+    const double e = fma(1.5, w2, fma(-2.0, w3, 0.5 * w4));
+    double sL = fma(b, b, Em);
+    double sC = fma(d, d, E0);
+    double sR = fma(e, e, Ep);
+    sL *= sL;
+    sC *= sC;
+    sR *= sR;
+    const double PLC = sL * sC, PLR = sL * sR, PCR = sC * sR;
+    const double h1 = 0.1 * w2, h5 = 0.5 * w2, h11 = (11.0 / 60.0) * w2;
+    // u^-_{p+1/2}: 3/10 (2w2 + 5w3 - w4)/6, 6/10 (-w1 + 5w2 + 2w3)/6, 1/10 (2w0 - 7w1 + 11w2)/6
+    const double cR = fma(-0.05, w4, fma(0.25, w3, h1));
+    const double cC = fma(0.2, w3, fma(-0.1, w1, h5));
+    const double cL = fma(2.0 / 60.0, w0, fma(-7.0 / 60.0, w1, h11));
+    // u^+_{p-1/2}: 1/10 (11w2 - 7w3 + 2w4)/6, 6/10 (2w1 + 5w2 - w3)/6, 3/10 (-w0 + 5w1 + 2w2)/6
+    const double dR = fma(2.0 / 60.0, w4, fma(-7.0 / 60.0, w3, h11));
+    const double dC = fma(0.2, w1, fma(-0.1, w3, h5));
+    const double dL = fma(-0.05, w0, fma(0.25, w1, h1));
+    const double nm = fma(PCR, cL, fma(PLR, cC, PLC * cR));
+    const double dm = fma(0.1, PCR, fma(0.6, PLR, 0.3 * PLC));
+    const double np = fma(PCR, dL, fma(PLR, dC, PLC * dR));
+    const double dp = fma(0.3, PCR, fma(0.6, PLR, 0.1 * PLC));
+    const double inv = recip(dm * dp);
+    um = nm * (dp * inv);
+    up = np * (dm * inv);
+}
+
+// f(u) = u (fa u + fb): Burgers (fa = 1/2, fb = 0) or advection (fa = 0, fb = a)
+MGK_HD double flux_f(double u, double fa, double fb) { return u * fma(fa, u, fb); }
+
+// Twice the Lax-Friedrichs flux of eq LFflux: f(uL) + f(uR) - alpha (uR - uL)
+MGK_HD double lf_flux2(double uL, double uR, double fa, double fb, double alpha)
+{
+    return fma(-alpha, uR - uL, flux_f(uL, fa, fb) + flux_f(uR, fa, fb));
+}
+
+// alpha_LF = max |lambda(u^{+-})| from m = max |u^{+-}|: with lambda = 2 fa u + fb
+// and one of fa, fb zero (Burgers or advection) it is 2|fa| m + |fb|
+MGK_HD double lf_alpha(double m, double fa, double fb) { return fma(2.0 * fabs(fa), m, fabs(fb)); }
+
+// Stage combinations of eq SSPRK1/2/3 (Shu-Osher form), x = u^n, v = the
+// previous stage, A = A(v):
+//   first stage (all):  x + dt A
+//   SSPRK2 second:      x/2 + v/2 + (dt/2) A           (hdt = dt/2)
+//   SSPRK3 second:      3x/4 + v/4 + (dt/4) A          (qdt = dt/4)
+//   SSPRK3 third:       x/3 + 2v/3 + (2dt/3) A         (tdt = 2dt/3)
+MGK_HD double rk_first(double x, double A, double dt) { return fma(dt, A, x); }
+MGK_HD double rk2_second(double x, double v, double A, double hdt) { return fma(hdt, A, fma(0.5, v, 0.5 * x)); }
+MGK_HD double rk3_second(double x, double v, double A, double qdt) { return fma(qdt, A, fma(0.25, v, 0.75 * x)); }
+MGK_HD double rk3_third(double x, double v, double A, double tdt)
+{
+    return fma(tdt, A, fma(2.0 / 3.0, v, (1.0 / 3.0) * x));
+}
+
+}  // namespace mgk

@@ -9,8 +9,8 @@ namespace mgk {
 // Constants of Phi for one scheme: f(u) = u (fa u + fb), lambda(u) = 2 fa u + fb
 // (Burgers: fa = 1/2, fb = 0; linear advection: fa = 0, fb = a).
 struct PhiConst {
-    double fa, fb, two_fa;
-    double inv_dx;
+    double fa, fb;
+    double half_inv_dx;  // 1/(2 dx): the flux difference uses twice the LF flux
     double eps;
     double alpha_fixed;  // > 0 replaces the global alpha_LF
 };
@@ -64,18 +64,32 @@ struct KernelCfg {
     int nw;   // waves per workgroup (= per line)
 };
 
-// compiled (cells per thread, waves) pairs, smallest line capacity first
+// compiled (cells per thread, waves) pairs.  Many-line launches use few
+// threads per line with several cells each (instruction-level parallelism,
+// registers); launches with few lines (coarse levels, the serial coarsest
+// solve) use more threads per line to shorten each step.
 #define MGK_CFG_LIST(X) \
     X(1, 1)             \
     X(2, 1)             \
     X(4, 1)             \
+    X(1, 2)             \
+    X(2, 2)             \
     X(4, 2)             \
+    X(1, 4)             \
+    X(2, 4)             \
     X(4, 4)             \
     X(8, 4)             \
+    X(1, 8)             \
+    X(2, 8)             \
     X(4, 8)             \
-    X(8, 8)
+    X(8, 8)             \
+    X(1, 16)            \
+    X(2, 16)
 
-inline size_t smem_bytes(int nx, int nw) { return sizeof(double) * ((size_t)nx + 2 * 64 * (size_t)nw + (size_t)nw); }
+inline size_t smem_bytes(int cpt, int nw)
+{
+    return sizeof(double) * (64 * (size_t)nw * (size_t)cpt + 2 * 64 * (size_t)nw + 3 * (size_t)nw);
+}
 
 hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
 hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s);

@@ -6,14 +6,13 @@
 // registers, the line is mirrored into LDS once per Runge-Kutta stage so that
 // threads can read their 3-cell halo (periodic wrap by index), and the global
 // Lax-Friedrichs coefficient alpha_LF of the stage is a workgroup max
-// reduction (wave shuffles, then one LDS slot per wave).
+// reduction (DPP within each wave, then one LDS slot per wave).
 //
 // Per RK stage (sec 2.2) a thread:
 //   1. writes its cells to LDS, barrier;
 //   2. reads its halo and reconstructs u^-_{j+1/2} and u^+_{j-1/2} for each of
-//      its cells (sec 2.1.1; WENO5 smoothness indicators shared between the
-//      two reconstructions of a cell and between neighbouring cells), takes the
-//      local max of |lambda|, publishes its two boundary reconstructions,
+//      its cells (sec 2.1.1; the per-cell arithmetic is in cell_math.h), takes
+//      the local max of |lambda|, publishes its two boundary reconstructions,
 //      barrier;
 //   3. reads alpha_LF and its neighbours' boundary reconstructions, forms the
 //      LF fluxes of its CPT+1 interfaces (eq LFflux) and the stage update.
@@ -25,6 +24,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "cell_math.h"
 #include "sweep.h"
 
 namespace mgk {
@@ -35,11 +35,30 @@ __device__ __forceinline__ int wrapi(int i, int n)
     return r < 0 ? r + n : r;
 }
 
+// Max over the 64 lanes of a wave, returned uniformly (NaN-ignoring like fmax).
+// DPP moves within quads, half-rows and rows, then the row broadcasts of lanes
+// 15 and 31 leave the maximum in lane 63, which is read back as a scalar.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __double2loint(v);
+    const int hi = __double2hiint(v);
+    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi2, lo2);
+}
+
 __device__ __forceinline__ double wave_max(double v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmax(v, dpp_move<0xb1, 0xf>(v));   // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_move<0x4e, 0xf>(v));   // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_move<0x141, 0xf>(v));  // row_half_mirror
+    v = fmax(v, dpp_move<0x140, 0xf>(v));  // row_mirror
+    v = fmax(v, dpp_move<0x142, 0xa>(v));  // row_bcast:15 into rows 1 and 3
+    v = fmax(v, dpp_move<0x143, 0xc>(v));  // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -49,16 +68,20 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Geometry of one thread inside its line.
+// Geometry of one thread inside its line.  Thread t owns cells
+// j0 = t*CPT .. j0+CPT-1; threads past the end of the line (and the cells past
+// nx of the last, ragged thread) compute on scratch values that are never
+// stored and never enter alpha_LF.
 template <int CPT, int NW>
 struct Geo {
     int nx;
     int t;        // thread index in the line
     int j0;       // first cell
-    int nvalid;   // cells owned (CPT, or fewer for the last thread)
+    int nvalid;   // cells owned inside the line (CPT, fewer for the ragged thread, 0 past the end)
     int left;     // thread owning the cell before j0 (periodic)
     int right;    // thread owning the cell after the last owned one (periodic)
-    bool active;
+    bool active;  // owns at least one cell
+    bool ragged;  // owns fewer than CPT cells
     int halo[6];  // line indices of window positions 0,1,2 and CPT+3..CPT+5
 
     __device__ __forceinline__ void init(int nx_)
@@ -69,8 +92,9 @@ struct Geo {
         active = t < nact;
         j0 = t * CPT;
         nvalid = active ? min(CPT, nx - j0) : 0;
-        left = (t == 0) ? nact - 1 : t - 1;
-        right = (t == nact - 1) ? 0 : t + 1;
+        ragged = active && nvalid < CPT;
+        left = active ? ((t == 0) ? nact - 1 : t - 1) : t;
+        right = active ? ((t == nact - 1) ? 0 : t + 1) : t;
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
             halo[p] = wrapi(j0 - 3 + p, nx);
@@ -79,184 +103,144 @@ struct Geo {
     }
 };
 
-// Shared-memory layout: line[nx] | bm[NT] | bp[NT] | wred[NW]
-template <int NW>
+// Shared-memory layout: line[64*NW*CPT] | bm[64*NW] | bp[64*NW] | wred[NW] | amax[2*NW].
+// The line array covers every thread's cells, so stage values are written
+// without predicates; slots nx.. are scratch.  amax holds the per-wave maxima
+// of the alpha_LF reduction, double-buffered by stage parity.
+template <int CPT, int NW>
 struct Smem {
     double* line;
     double* bm;
     double* bp;
     double* wred;
-    __device__ __forceinline__ void init(double* base, int nx)
+    double* amax;
+    __device__ __forceinline__ void init(double* base)
     {
         line = base;
-        bm = base + nx;
+        bm = base + 64 * NW * CPT;
         bp = bm + 64 * NW;
         wred = bp + 64 * NW;
+        amax = wred + NW;
     }
 };
 
 // A(V) for the thread's cells: eq spaceDisc with the LF flux (eq LFflux) and
 // either the trivial (K = 0) or the WENO5 (K = 2) reconstruction.
-template <int CPT, int NW, int K>
+// RAG: the line length is not a multiple of CPT, so one thread is ragged.
+// par selects the alpha_LF slots of this stage (the other half is still read
+// by slow waves of the previous stage until the first barrier).
+template <int CPT, int NW, int K, bool RAG>
 __device__ __forceinline__ void op_A(const double (&V)[CPT], double (&A)[CPT], const Geo<CPT, NW>& g,
-                                     const Smem<NW>& sm, const PhiConst& pc)
+                                     const Smem<CPT, NW>& sm, const PhiConst& pc, int& par)
 {
-    if (g.active) {
 #pragma unroll
-        for (int q = 0; q < CPT; ++q)
-            if (q < g.nvalid) sm.line[g.j0 + q] = V[q];
-    }
+    for (int q = 0; q < CPT; ++q) sm.line[g.j0 + q] = V[q];
     __syncthreads();
 
+    // window w[p] = cell j0 - 3 + p, p = 0..CPT+5
+    double w[CPT + 6];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) w[3 + q] = V[q];
+    if (RAG && g.ragged) {
+        // positions past the end of the line wrap around to its first cells
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+            if (q >= g.nvalid) w[3 + q] = sm.line[wrapi(g.j0 + q, g.nx)];
+    }
     double um[CPT], up[CPT];
-    double lmax = 0.0;
-    if (g.active) {
-        // window w[p] = cell j0 - 3 + p, p = 0..CPT+5
-        double w[CPT + 6];
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) w[3 + q] = V[q];
-        if (g.nvalid < CPT) {
-            // last thread of a ragged line: positions past the end wrap around
-#pragma unroll
-            for (int q = 0; q < CPT; ++q)
-                if (q >= g.nvalid) w[3 + q] = sm.line[wrapi(g.j0 + q, g.nx)];
-        }
-        if (K == 0) {
-#pragma unroll
-            for (int q = 0; q < CPT; ++q) {
-                um[q] = w[3 + q];
-                up[q] = w[3 + q];
-            }
-        } else {
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-                w[p] = sm.line[g.halo[p]];
-                w[CPT + 3 + p] = sm.line[g.halo[3 + p]];
-            }
-            // Smoothness indicators in the Jiang-Shu form of the printed B_r
-            // (eq B): for the stencil ending at p (cells p-2, p-1, p)
-            //   bL[p] = 13/12 (w[p-2] - 2w[p-1] + w[p])^2 + 1/4 (w[p-2] - 4w[p-1] + 3w[p])^2,
-            // for the centred stencil (p-1, p, p+1)
-            //   bC[p] = 13/12 (w[p-1] - 2w[p] + w[p+1])^2 + 1/4 (w[p+1] - w[p-1])^2,
-            // and the stencil starting at p is bL[p+2].
-            double E[CPT + 6], bL[CPT + 6], bC[CPT + 6];
-#pragma unroll
-            for (int p = 1; p <= CPT + 4; ++p) {
-                const double d2 = fma(-2.0, w[p], w[p - 1] + w[p + 1]);
-                E[p] = (13.0 / 12.0) * d2 * d2;
-            }
-#pragma unroll
-            for (int p = 3; p <= CPT + 4; ++p) {
-                const double b = fma(3.0, w[p], fma(-4.0, w[p - 1], w[p - 2]));
-                bL[p] = fma(0.25 * b, b, E[p - 1]);
-            }
-#pragma unroll
-            for (int p = 3; p <= CPT + 2; ++p) {
-                const double d = w[p + 1] - w[p - 1];
-                bC[p] = fma(0.25 * d, d, E[p]);
-            }
-#pragma unroll
-            for (int q = 0; q < CPT; ++q) {
-                const int p = q + 3;
-                double sL = pc.eps + bL[p];
-                double sC = pc.eps + bC[p];
-                double sR = pc.eps + bL[p + 2];
-                sL *= sL;
-                sC *= sC;
-                sR *= sR;
-                // alpha_r = d_r / s_r (eq omega); multiplying numerator and
-                // denominator of sum(alpha_r p_r)/sum(alpha_r) by sL sC sR leaves
-                // one division per reconstruction.
-                const double PLC = sL * sC, PLR = sL * sR, PCR = sC * sR;
-                // u^-_{j+1/2}: d = 3/10 (stencil j..j+2), 6/10 (centred), 1/10 (j-2..j);
-                // candidates of eq C with d_r folded in.
-                const double cR = fma(-0.05, w[p + 2], fma(0.25, w[p + 1], 0.1 * w[p]));
-                const double cC = fma(0.2, w[p + 1], fma(0.5, w[p], -0.1 * w[p - 1]));
-                const double cL = fma(11.0 / 60.0, w[p], fma(-7.0 / 60.0, w[p - 1], (2.0 / 60.0) * w[p - 2]));
-                const double nm = fma(PCR, cL, fma(PLR, cC, PLC * cR));
-                const double dm = fma(0.1, PCR, fma(0.6, PLR, 0.3 * PLC));
-                um[q] = nm / dm;
-                // u^+_{j-1/2}: mirror image, d = 1/10 (j..j+2), 6/10, 3/10 (j-2..j)
-                const double dR = fma(11.0 / 60.0, w[p], fma(-7.0 / 60.0, w[p + 1], (2.0 / 60.0) * w[p + 2]));
-                const double dC = fma(0.2, w[p - 1], fma(0.5, w[p], -0.1 * w[p + 1]));
-                const double dL = fma(-0.05, w[p - 2], fma(0.25, w[p - 1], 0.1 * w[p]));
-                const double np = fma(PCR, dL, fma(PLR, dC, PLC * dR));
-                const double dp = fma(0.3, PCR, fma(0.6, PLR, 0.1 * PLC));
-                up[q] = np / dp;
-            }
-        }
+    if (K == 0) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
-            lmax = fmax(lmax, fabs(fma(pc.two_fa, um[q], pc.fb)));
-            lmax = fmax(lmax, fabs(fma(pc.two_fa, up[q], pc.fb)));
+            um[q] = w[3 + q];
+            up[q] = w[3 + q];
         }
-        double last = um[0];
+    } else {
 #pragma unroll
-        for (int q = 1; q < CPT; ++q)
-            if (q == g.nvalid - 1) last = um[q];
-        sm.bm[g.t] = last;
-        sm.bp[g.t] = up[0];
+        for (int p = 0; p < 3; ++p) {
+            w[p] = sm.line[g.halo[p]];
+            w[CPT + 3 + p] = sm.line[g.halo[3 + p]];
+        }
+        double E[CPT + 6];
+#pragma unroll
+        for (int p = 2; p <= CPT + 3; ++p) E[p] = weno5_e(w[p - 1], w[p], w[p + 1], pc.eps);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int p = q + 3;
+            weno5_cell(w[p - 2], w[p - 1], w[p], w[p + 1], w[p + 2], E[p - 1], E[p], E[p + 1], um[q], up[q]);
+        }
     }
+    double lmax = 0.0;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) lmax = fmax(lmax, fmax(fabs(um[q]), fabs(up[q])));
+    double last = um[CPT - 1];
+    if (RAG && g.ragged) {
+#pragma unroll
+        for (int q = 0; q < CPT - 1; ++q)
+            if (q == g.nvalid - 1) last = um[q];
+    }
+    sm.bm[g.t] = last;
+    sm.bp[g.t] = up[0];
+    // alpha_LF: max|u^{+-}| over the line (exact, order independent): wave max,
+    // then one slot per wave (double-buffered by stage parity)
+    if (!g.active) lmax = 0.0;
     lmax = wave_max(lmax);
-    if ((threadIdx.x & 63) == 0) sm.wred[threadIdx.x >> 6] = lmax;
+    if (NW > 1 && (threadIdx.x & 63) == 0) sm.amax[par * NW + (threadIdx.x >> 6)] = lmax;
     __syncthreads();
 
     double alpha = pc.alpha_fixed;
     if (!(alpha > 0.0)) {
-        alpha = sm.wred[0];
+        if (NW > 1) {
 #pragma unroll
-        for (int w = 1; w < NW; ++w) alpha = fmax(alpha, sm.wred[w]);
-    }
-    if (g.active) {
-        const double hma = -0.5 * alpha;
-        const double uml = sm.bm[g.left];
-        const double upr = sm.bp[g.right];
-        double F[CPT + 1];
-#pragma unroll
-        for (int q = 0; q <= CPT; ++q) {
-            const double uL = (q == 0) ? uml : um[q - 1];
-            const double uR = (q == CPT) ? upr : up[q];
-            const double fL = uL * fma(pc.fa, uL, pc.fb);
-            const double fR = uR * fma(pc.fa, uR, pc.fb);
-            F[q] = fma(hma, uR - uL, 0.5 * (fR + fL));
+            for (int w2 = 0; w2 < NW; ++w2) lmax = fmax(lmax, sm.amax[par * NW + w2]);
         }
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) A[q] = (F[q] - F[q + 1]) * pc.inv_dx;
+        alpha = lf_alpha(lmax, pc.fa, pc.fb);
     }
+    par ^= 1;
+    const double uml = sm.bm[g.left];
+    const double upr = sm.bp[g.right];
+    double F[CPT + 1];
+#pragma unroll
+    for (int q = 0; q <= CPT; ++q) {
+        const double uL = (q == 0) ? uml : um[q - 1];
+        const double uR = (q == CPT) ? upr : up[q];
+        F[q] = lf_flux2(uL, uR, pc.fa, pc.fb, alpha);
+    }
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) A[q] = (F[q] - F[q + 1]) * pc.half_inv_dx;
 }
 
 // x <- Phi(x) with step dt (eq SSPRK1/2/3)
-template <int CPT, int NW, int K, int ST>
-__device__ __forceinline__ void phi(double (&x)[CPT], double dt, const Geo<CPT, NW>& g, const Smem<NW>& sm,
-                                    const PhiConst& pc)
+template <int CPT, int NW, int K, int ST, bool RAG>
+__device__ __forceinline__ void phi(double (&x)[CPT], double dt, const Geo<CPT, NW>& g, const Smem<CPT, NW>& sm,
+                                    const PhiConst& pc, int& par)
 {
     double A[CPT];
     if (ST == 1) {
-        op_A<CPT, NW, K>(x, A, g, sm, pc);
+        op_A<CPT, NW, K, RAG>(x, A, g, sm, pc, par);
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) x[q] = fma(dt, A[q], x[q]);
+        for (int q = 0; q < CPT; ++q) x[q] = rk_first(x[q], A[q], dt);
     } else if (ST == 2) {
         double v[CPT];
-        op_A<CPT, NW, K>(x, A, g, sm, pc);
+        op_A<CPT, NW, K, RAG>(x, A, g, sm, pc, par);
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) v[q] = fma(dt, A[q], x[q]);
-        op_A<CPT, NW, K>(v, A, g, sm, pc);
+        for (int q = 0; q < CPT; ++q) v[q] = rk_first(x[q], A[q], dt);
+        op_A<CPT, NW, K, RAG>(v, A, g, sm, pc, par);
         const double hdt = 0.5 * dt;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) x[q] = fma(hdt, A[q], fma(0.5, v[q], 0.5 * x[q]));
+        for (int q = 0; q < CPT; ++q) x[q] = rk2_second(x[q], v[q], A[q], hdt);
     } else {
         double v[CPT];
-        op_A<CPT, NW, K>(x, A, g, sm, pc);
+        op_A<CPT, NW, K, RAG>(x, A, g, sm, pc, par);
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) v[q] = fma(dt, A[q], x[q]);
-        op_A<CPT, NW, K>(v, A, g, sm, pc);
+        for (int q = 0; q < CPT; ++q) v[q] = rk_first(x[q], A[q], dt);
+        op_A<CPT, NW, K, RAG>(v, A, g, sm, pc, par);
         const double qdt = 0.25 * dt;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) v[q] = fma(qdt, A[q], fma(0.25, v[q], 0.75 * x[q]));
-        op_A<CPT, NW, K>(v, A, g, sm, pc);
+        for (int q = 0; q < CPT; ++q) v[q] = rk3_second(x[q], v[q], A[q], qdt);
+        op_A<CPT, NW, K, RAG>(v, A, g, sm, pc, par);
         const double tdt = (2.0 / 3.0) * dt;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) x[q] = fma(tdt, A[q], fma(2.0 / 3.0, v[q], (1.0 / 3.0) * x[q]));
+        for (int q = 0; q < CPT; ++q) x[q] = rk3_third(x[q], v[q], A[q], tdt);
     }
 }
 
@@ -307,7 +291,7 @@ __device__ __forceinline__ void copy_line(const double* src, double* dst, const 
 // sum of squares of (a - b) over the line, in a fixed order; valid in thread 0
 template <int CPT, int NW>
 __device__ __forceinline__ double line_sqdiff(const double (&a)[CPT], const double* b, const Geo<CPT, NW>& g,
-                                              const Smem<NW>& sm)
+                                              const Smem<CPT, NW>& sm)
 {
     double s = 0.0;
     if (g.active) {
@@ -319,7 +303,6 @@ __device__ __forceinline__ double line_sqdiff(const double (&a)[CPT], const doub
             }
     }
     s = wave_sum(s);
-    __syncthreads();  // wred may still be read as alpha slots
     if ((threadIdx.x & 63) == 0) sm.wred[threadIdx.x >> 6] = s;
     __syncthreads();
     double tot = 0.0;
@@ -330,15 +313,16 @@ __device__ __forceinline__ double line_sqdiff(const double (&a)[CPT], const doub
 }
 
 // One chunk (one line) per workgroup.  See SweepArgs for the roles.
-template <int CPT, int NW, int K, int ST>
+template <int CPT, int NW, int K, int ST, bool RAG>
 __global__ __launch_bounds__(64 * NW) void sweep_kernel(SweepArgs a)
 {
     if (a.flag != nullptr && *a.flag != 0) return;
     extern __shared__ double smem_raw[];
-    Smem<NW> sm;
-    sm.init(smem_raw, a.nx);
+    Smem<CPT, NW> sm;
+    sm.init(smem_raw);
     Geo<CPT, NW> g;
     g.init(a.nx);
+    int par = 0;
     const int64_t nx = a.nx;
     const int c = blockIdx.x;
 
@@ -363,20 +347,20 @@ __global__ __launch_bounds__(64 * NW) void sweep_kernel(SweepArgs a)
 
     const int64_t n0 = (int64_t)c * a.m;
     for (int j = 1; j <= a.nsteps; ++j) {
-        phi<CPT, NW, K, ST>(x, a.dt, g, sm, a.pc);
+        phi<CPT, NW, K, ST, RAG>(x, a.dt, g, sm, a.pc, par);
         if (a.g != nullptr) add_line(x, a.g + (n0 + j) * nx, g);
         if (a.fout != nullptr) store_line(x, a.fout + (n0 + j) * nx, g);
     }
 
     if (a.end_mode == END_NONE) return;
     if (a.end_mode == END_PHI) {
-        phi<CPT, NW, K, ST>(x, a.dt, g, sm, a.pc);
+        phi<CPT, NW, K, ST, RAG>(x, a.dt, g, sm, a.pc, par);
         store_line(x, a.side_out + (int64_t)c * nx, g);
         return;
     }
     // one more step to the chunk's end C-point n1 = (c+1) m
     const int64_t n1 = n0 + a.m;
-    phi<CPT, NW, K, ST>(x, a.dt, g, sm, a.pc);
+    phi<CPT, NW, K, ST, RAG>(x, a.dt, g, sm, a.pc, par);
     if (a.g != nullptr) add_line(x, a.g + n1 * nx, g);
     // the current value at that C-point
     const double* cnext = a.cref + (int64_t)(c + 1) * a.cref_stride * nx;
@@ -398,7 +382,7 @@ __global__ __launch_bounds__(64 * NW) void sweep_kernel(SweepArgs a)
     else store_line(x, a.uc_out + (int64_t)(c + 1) * nx, g);
     double y[CPT];
     load_line(y, cstart, g);
-    phi<CPT, NW, K, ST>(y, a.dt_next, g, sm, a.pc);
+    phi<CPT, NW, K, ST, RAG>(y, a.dt_next, g, sm, a.pc, par);
     if (g.active) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) y[q] = x[q] - y[q];
@@ -465,11 +449,11 @@ __global__ void reduce_norm_kernel(const double* partial, int n, double* hist, i
 // host-side dispatch over the compiled configurations
 // ---------------------------------------------------------------------------
 
-template <int CPT, int NW, int K, int ST>
+template <int CPT, int NW, int K, int ST, bool RAG>
 static hipError_t launch_one(const SweepArgs& a, hipStream_t s)
 {
-    const size_t shmem = smem_bytes(a.nx, NW);
-    auto fn = sweep_kernel<CPT, NW, K, ST>;
+    const size_t shmem = smem_bytes(CPT, NW);
+    auto fn = sweep_kernel<CPT, NW, K, ST, RAG>;
     if (shmem > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
@@ -478,17 +462,26 @@ static hipError_t launch_one(const SweepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int CPT, int NW, bool RAG>
+static hipError_t launch_rag(const SweepArgs& a, int k, int st, hipStream_t s)
+{
+    if (k == 0) {
+        if (st == 1) return launch_one<CPT, NW, 0, 1, RAG>(a, s);
+        if (st == 2) return launch_one<CPT, NW, 0, 2, RAG>(a, s);
+        return launch_one<CPT, NW, 0, 3, RAG>(a, s);
+    }
+    if (st == 1) return launch_one<CPT, NW, 2, 1, RAG>(a, s);
+    if (st == 2) return launch_one<CPT, NW, 2, 2, RAG>(a, s);
+    return launch_one<CPT, NW, 2, 3, RAG>(a, s);
+}
+
 template <int CPT, int NW>
 static hipError_t launch_cfg(const SweepArgs& a, int k, int st, hipStream_t s)
 {
-    if (k == 0) {
-        if (st == 1) return launch_one<CPT, NW, 0, 1>(a, s);
-        if (st == 2) return launch_one<CPT, NW, 0, 2>(a, s);
-        return launch_one<CPT, NW, 0, 3>(a, s);
+    if constexpr (CPT > 1) {
+        if (a.nx % CPT != 0) return launch_rag<CPT, NW, true>(a, k, st, s);
     }
-    if (st == 1) return launch_one<CPT, NW, 2, 1>(a, s);
-    if (st == 2) return launch_one<CPT, NW, 2, 2>(a, s);
-    return launch_one<CPT, NW, 2, 3>(a, s);
+    return launch_rag<CPT, NW, false>(a, k, st, s);
 }
 
 hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s)

@@ -101,8 +101,8 @@ def load(path: str = LIB_PATH):
     L.mgrit_last_error.restype = C.c_char_p
     L.mgrit_set_profiling.argtypes = [C.c_int]
     L.mgrit_get_profile.argtypes = [C.POINTER(ProfileEntry), C.c_int]
-    L.mgrit_kernel_config.argtypes = [i32, C.POINTER(i32), C.POINTER(i32)]
-    L.mgrit_set_kernel_config.argtypes = [i32, i32, i32, i32]
+    L.mgrit_kernel_config.argtypes = [i32, i32, C.POINTER(i32), C.POINTER(i32)]
+    L.mgrit_set_kernel_config.argtypes = [i32, i32, i32, i32, i32]
     for name in EXPORTED:
         if name in ("mgrit_last_error", "mgrit_set_profiling", "mgrit_workspace_bytes"):
             continue
@@ -213,11 +213,15 @@ def get_profile() -> dict:
                                     cell_steps=arr[i].cell_steps) for i in range(len(KERNEL_CLASSES))}
 
 
-def kernel_config(nx: int):
+def kernel_config(nx: int, nlines: int = 1 << 20):
     c, w = C.c_int32(0), C.c_int32(0)
-    _check(load().mgrit_kernel_config(nx, C.byref(c), C.byref(w)))
+    _check(load().mgrit_kernel_config(nx, nlines, C.byref(c), C.byref(w)))
     return c.value, w.value
 
 
-def set_kernel_config(nx_lo: int, nx_hi: int, cpt: int, waves: int):
-    _check(load().mgrit_set_kernel_config(nx_lo, nx_hi, cpt, waves))
+def set_kernel_config(nx_lo: int, nx_hi: int, cpt: int, waves: int, latency: bool = False):
+    _check(load().mgrit_set_kernel_config(nx_lo, nx_hi, 1 if latency else 0, cpt, waves))
+
+
+def clear_kernel_config():
+    _check(load().mgrit_set_kernel_config(0, 0, 0, 0, 0))

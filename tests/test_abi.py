@@ -81,9 +81,18 @@ def test_kernel_config_choice(lib):
     from paper_2104_09404_amd import mgrit
 
     assert mgrit.kernel_config(64) == (1, 1)
-    cpt, w = mgrit.kernel_config(1024)
-    assert cpt * w * 64 >= 1024
-    cpt, w = mgrit.kernel_config(1000)
-    assert cpt * w * 64 >= 1000
+    for nx in (1000, 1024, 4096):
+        for nlines in (1, 64, 512):
+            cpt, w = mgrit.kernel_config(nx, nlines)
+            assert cpt * w * 64 >= nx
+    # few lines: more threads per line than for many lines
+    c1, w1 = mgrit.kernel_config(1024, 1)
+    c2, w2 = mgrit.kernel_config(1024, 512)
+    assert w1 > w2 and c1 < c2
     with pytest.raises(mgrit.MgritError):
         mgrit.kernel_config(1 << 20)
+    with pytest.raises(mgrit.MgritError):
+        mgrit.set_kernel_config(1024, 1024, 4, 2)  # 512 cells do not cover 1024
+    mgrit.set_kernel_config(1024, 1024, 8, 4)
+    assert mgrit.kernel_config(1024, 512) == (8, 4)
+    mgrit.clear_kernel_config()

@@ -306,12 +306,12 @@ def test_launch_configurations_agree_bitwise(gpu):
     s = gpu.scheme(nx)
     dt = 0.5 / nx / np.max(np.abs(u))
     outs = []
-    for cpt, w in [(4, 4), (8, 4), (4, 8), (8, 8)]:
-        gpu.set_kernel_config(nx, nx, cpt, w)
+    for cpt, w in [(4, 4), (8, 4), (4, 8), (8, 8), (2, 8), (1, 16), (2, 16)]:
+        gpu.set_kernel_config(nx, nx, cpt, w, latency=False)
         out = T(np.zeros_like(u))
         gpu.phi(s, dt, T(u), out)
         outs.append(H(out))
-    gpu.set_kernel_config(0, 0, 0, 0)
+    gpu.clear_kernel_config()
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
 
