@@ -1,0 +1,107 @@
+// aux.hip -- small auxiliary kernels (initial fill, residual norms, flags)
+// and the dispatch of sweep launches to the per-scheme translation units.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sweep.h"
+
+namespace mgk {
+
+template <int K, int ST>
+hipError_t launch_sweep_ks(const SweepArgs& a, const KernelCfg& cfg, hipStream_t s);
+
+hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
+{
+    if (a.nchunks <= 0) return hipSuccess;
+    if (k == 0) {
+        if (stepper == 1) return launch_sweep_ks<0, 1>(a, cfg, s);
+        if (stepper == 2) return launch_sweep_ks<0, 2>(a, cfg, s);
+        return launch_sweep_ks<0, 3>(a, cfg, s);
+    }
+    if (stepper == 1) return launch_sweep_ks<2, 1>(a, cfg, s);
+    if (stepper == 2) return launch_sweep_ks<2, 2>(a, cfg, s);
+    return launch_sweep_ks<2, 3>(a, cfg, s);
+}
+
+
+// dst[b] = src for b < nlines (fill every node with the initial condition)
+__global__ void broadcast_kernel(const double* src, double* dst, int64_t nx, int64_t nlines)
+{
+    const int64_t total = nx * nlines;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i % nx];
+}
+
+// out = sqrt(sum r_i^2) in a fixed order (one workgroup)
+__global__ void sumsq_norm_kernel(const double* r, int64_t n, double* out)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s = fma(r[i], r[i], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
+__global__ void clear_ints_kernel(int* p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+// norm of the residual from per-chunk partial sums, in a fixed order; records
+// it at hist[*counter], advances the counter and raises the convergence flag
+__global__ void reduce_norm_kernel(const double* partial, int n, double* hist, int* counter, int* flag, double tol)
+{
+    if (*flag != 0) return;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double nrm = sqrt(red[0]);
+        const int k = *counter;
+        hist[k] = nrm;
+        *counter = k + 1;
+        if (tol >= 0.0 && nrm < tol) *flag = 1;
+    }
+}
+
+hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s)
+{
+    if (nlines <= 0) return hipSuccess;
+    const int64_t total = nx * nlines;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(broadcast_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, nx, nlines);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sumsq_norm_kernel, dim3(1), dim3(256), 0, s, r, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_ints(int* p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(clear_ints_kernel, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_norm(const double* partial, int n, double* hist, int* counter, int* flag, double tol,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_norm_kernel, dim3(1), dim3(256), 0, s, partial, n, hist, counter, flag, tol);
+    return hipGetLastError();
+}
+
+}  // namespace mgk

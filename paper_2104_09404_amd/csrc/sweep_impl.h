@@ -1,4 +1,6 @@
-// sweep.hip -- gfx950 kernels for the MGRIT hot path.
+// sweep_impl.h -- gfx950 kernels for the MGRIT hot path (included by the
+// sweep_k*_s*.hip translation units, one per reconstruction degree and
+// Runge-Kutta scheme, so that they compile in parallel).
 //
 // One workgroup owns one line (one time chunk at one level, or one independent
 // line) and steps it through several applications of the propagator Phi,
@@ -21,6 +23,7 @@
 // exactly and the sum of u is conserved to round-off.
 //
 // Arithmetic is FP64 only; no MFMA (this is stencil work, not a contraction).
+#pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -312,9 +315,10 @@ __device__ __forceinline__ double line_sqdiff(const double (&a)[CPT], const doub
     return tot;
 }
 
-// One chunk (one line) per workgroup.  See SweepArgs for the roles.
-template <int CPT, int NW, int K, int ST, bool RAG>
-__global__ __launch_bounds__(64 * NW) void sweep_kernel(SweepArgs a)
+// One chunk (one line) per workgroup.  See SweepArgs for the roles; END is
+// the compile-time end mode.
+template <int CPT, int NW, int K, int ST, bool RAG, int END>
+__device__ __forceinline__ void sweep_body(const SweepArgs& a)
 {
     if (a.flag != nullptr && *a.flag != 0) return;
     extern __shared__ double smem_raw[];
@@ -339,7 +343,7 @@ __global__ __launch_bounds__(64 * NW) void sweep_kernel(SweepArgs a)
     }
     // the chunk's starting C-point (the source of the coarse step of END_RESTRICT)
     const double* cstart = (a.ystart != nullptr) ? a.ystart + (int64_t)c * a.ystart_stride * nx : src;
-    if (a.end_mode == END_RESTRICT && c == 0) {
+    if (END == END_RESTRICT && c == 0) {
         // coarse node 0: u_c^0 = u^0, g_c^0 = g^0 (= u^0 at level 0)
         copy_line(cstart, a.uc_out, g);
         copy_line(a.g != nullptr ? a.g : cstart, a.gc_out, g);
@@ -352,8 +356,8 @@ __global__ __launch_bounds__(64 * NW) void sweep_kernel(SweepArgs a)
         if (a.fout != nullptr) store_line(x, a.fout + (n0 + j) * nx, g);
     }
 
-    if (a.end_mode == END_NONE) return;
-    if (a.end_mode == END_PHI) {
+    if constexpr (END == END_NONE) return;
+    if constexpr (END == END_PHI) {
         phi<CPT, NW, K, ST, RAG>(x, a.dt, g, sm, a.pc, par);
         store_line(x, a.side_out + (int64_t)c * nx, g);
         return;
@@ -373,7 +377,7 @@ __global__ __launch_bounds__(64 * NW) void sweep_kernel(SweepArgs a)
         for (int q = 0; q < CPT; ++q)
             if (q < g.nvalid) a.r_out[(int64_t)c * nx + g.j0 + q] = x[q] - cnext[g.j0 + q];
     }
-    if (a.end_mode == END_CSTEP) {
+    if constexpr (END == END_CSTEP) {
         if (a.side_out != nullptr) store_line(x, a.side_out + (int64_t)(c + 1) * nx, g);
         return;
     }
@@ -390,137 +394,76 @@ __global__ __launch_bounds__(64 * NW) void sweep_kernel(SweepArgs a)
     store_line(y, a.gc_out + (int64_t)(c + 1) * nx, g);
 }
 
-// ---------------------------------------------------------------------------
-// small auxiliary kernels
-// ---------------------------------------------------------------------------
 
-// dst[b] = src for b < nlines (fill every node with the initial condition)
-__global__ void broadcast_kernel(const double* src, double* dst, int64_t nx, int64_t nlines)
+// The four roles as separately named kernels (so that profiles tell them apart)
+template <int CPT, int NW, int K, int ST, bool RAG>
+__global__ __launch_bounds__(64 * NW) void relax_f_kernel(SweepArgs a)
 {
-    const int64_t total = nx * nlines;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i % nx];
+    sweep_body<CPT, NW, K, ST, RAG, END_NONE>(a);
 }
-
-// out = sqrt(sum r_i^2) in a fixed order (one workgroup)
-__global__ void sumsq_norm_kernel(const double* r, int64_t n, double* out)
-{
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s = fma(r[i], r[i], s);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = sqrt(red[0]);
-}
-
-__global__ void clear_ints_kernel(int* p, int n)
-{
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
-}
-
-// norm of the residual from per-chunk partial sums, in a fixed order; records
-// it at hist[*counter], advances the counter and raises the convergence flag
-__global__ void reduce_norm_kernel(const double* partial, int n, double* hist, int* counter, int* flag, double tol)
-{
-    if (*flag != 0) return;
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double nrm = sqrt(red[0]);
-        const int k = *counter;
-        hist[k] = nrm;
-        *counter = k + 1;
-        if (tol >= 0.0 && nrm < tol) *flag = 1;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// host-side dispatch over the compiled configurations
-// ---------------------------------------------------------------------------
 
 template <int CPT, int NW, int K, int ST, bool RAG>
-static hipError_t launch_one(const SweepArgs& a, hipStream_t s)
+__global__ __launch_bounds__(64 * NW) void relax_fc_kernel(SweepArgs a)
 {
-    const size_t shmem = smem_bytes(CPT, NW);
-    auto fn = sweep_kernel<CPT, NW, K, ST, RAG>;
+    sweep_body<CPT, NW, K, ST, RAG, END_CSTEP>(a);
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG>
+__global__ __launch_bounds__(64 * NW) void relax_fr_kernel(SweepArgs a)
+{
+    sweep_body<CPT, NW, K, ST, RAG, END_RESTRICT>(a);
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG>
+__global__ __launch_bounds__(64 * NW) void phi_kernel(SweepArgs a)
+{
+    sweep_body<CPT, NW, K, ST, RAG, END_PHI>(a);
+}
+
+// ---------------------------------------------------------------------------
+// launch over the compiled configurations
+// ---------------------------------------------------------------------------
+template <class Fn>
+static hipError_t launch_fn(Fn fn, const SweepArgs& a, int nw, size_t shmem, hipStream_t s)
+{
     if (shmem > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(a.nchunks), dim3(64 * NW), shmem, s, a);
+    hipLaunchKernelGGL(fn, dim3(a.nchunks), dim3(64 * nw), shmem, s, a);
     return hipGetLastError();
 }
 
-template <int CPT, int NW, bool RAG>
-static hipError_t launch_rag(const SweepArgs& a, int k, int st, hipStream_t s)
+template <int CPT, int NW, int K, int ST, bool RAG>
+static hipError_t launch_role(const SweepArgs& a, hipStream_t s)
 {
-    if (k == 0) {
-        if (st == 1) return launch_one<CPT, NW, 0, 1, RAG>(a, s);
-        if (st == 2) return launch_one<CPT, NW, 0, 2, RAG>(a, s);
-        return launch_one<CPT, NW, 0, 3, RAG>(a, s);
+    const size_t shmem = smem_bytes(CPT, NW);
+    switch (a.end_mode) {
+    case END_NONE: return launch_fn(relax_f_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
+    case END_CSTEP: return launch_fn(relax_fc_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
+    case END_RESTRICT: return launch_fn(relax_fr_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
+    case END_PHI: return launch_fn(phi_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
+    default: return hipErrorInvalidValue;
     }
-    if (st == 1) return launch_one<CPT, NW, 2, 1, RAG>(a, s);
-    if (st == 2) return launch_one<CPT, NW, 2, 2, RAG>(a, s);
-    return launch_one<CPT, NW, 2, 3, RAG>(a, s);
 }
 
-template <int CPT, int NW>
-static hipError_t launch_cfg(const SweepArgs& a, int k, int st, hipStream_t s)
+template <int CPT, int NW, int K, int ST>
+static hipError_t launch_cfg(const SweepArgs& a, hipStream_t s)
 {
     if constexpr (CPT > 1) {
-        if (a.nx % CPT != 0) return launch_rag<CPT, NW, true>(a, k, st, s);
+        if (a.nx % CPT != 0) return launch_role<CPT, NW, K, ST, true>(a, s);
     }
-    return launch_rag<CPT, NW, false>(a, k, st, s);
+    return launch_role<CPT, NW, K, ST, false>(a, s);
 }
 
-hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
+template <int K, int ST>
+hipError_t launch_sweep_ks(const SweepArgs& a, const KernelCfg& cfg, hipStream_t s)
 {
-    if (a.nchunks <= 0) return hipSuccess;
 #define MGK_CASE(C, W) \
-    if (cfg.cpt == C && cfg.nw == W) return launch_cfg<C, W>(a, k, stepper, s);
+    if (cfg.cpt == C && cfg.nw == W) return launch_cfg<C, W, K, ST>(a, s);
     MGK_CFG_LIST(MGK_CASE)
 #undef MGK_CASE
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s)
-{
-    if (nlines <= 0) return hipSuccess;
-    const int64_t total = nx * nlines;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(broadcast_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, nx, nlines);
-    return hipGetLastError();
-}
-
-hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_t s)
-{
-    hipLaunchKernelGGL(sumsq_norm_kernel, dim3(1), dim3(256), 0, s, r, n, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_clear_ints(int* p, int n, hipStream_t s)
-{
-    hipLaunchKernelGGL(clear_ints_kernel, dim3(1), dim3(64), 0, s, p, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce_norm(const double* partial, int n, double* hist, int* counter, int* flag, double tol,
-                              hipStream_t s)
-{
-    hipLaunchKernelGGL(reduce_norm_kernel, dim3(1), dim3(256), 0, s, partial, n, hist, counter, flag, tol);
-    return hipGetLastError();
 }
 
 }  // namespace mgk
