@@ -530,3 +530,198 @@ int orc_mgrit(const orc_scheme* s, const orc_params* p, const double* u0, double
     free(mg.res);
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint of Phi and of serial time stepping                        */
+/* (not in the paper: the derivative of the scheme above, written by hand)    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Gradient of the WENO5 reconstruction v -> W(v) of orc_weno5_left, by the chain
+ * rule through the printed formulas:
+ *   W = sum_r omega_r p_r,  omega_r = alpha_r / S,  S = sum_r alpha_r,
+ *   alpha_r = d_r / (eps + beta_r)^2,  beta_r = q_r^T B_r q_r,  p_r = c_r . q_r
+ *   dW/dv = sum_r omega_r dp_r/dv + (1/S) sum_r (p_r - W) dalpha_r/dv,
+ *   dalpha_r/dv = -2 d_r / (eps + beta_r)^3 * 2 B_r q_r  (on the cells of stencil r).
+ */
+void orc_weno5_left_grad(const double* v, double eps, double* grad)
+{
+    double p[3], beta[3], alpha[3];
+    orc_weno5_candidates(v, p);
+    orc_weno5_beta(v, beta);
+    double S = 0.0;
+    for (int r = 0; r < 3; ++r) {
+        alpha[r] = WENO_D[r] / ((eps + beta[r]) * (eps + beta[r]));
+        S += alpha[r];
+    }
+    double W = 0.0;
+    for (int r = 0; r < 3; ++r) W += (alpha[r] / S) * p[r];
+    for (int j = 0; j < 5; ++j) grad[j] = 0.0;
+    for (int r = 0; r < 3; ++r) {
+        const double* q = v + 2 - r;
+        const double omega = alpha[r] / S;
+        const double e = eps + beta[r];
+        const double dalpha_dbeta = -2.0 * WENO_D[r] / (e * e * e);
+        for (int a = 0; a < 3; ++a) {
+            double dbeta = 0.0; /* d beta_r / d q_a = 2 (B_r q)_a */
+            for (int b = 0; b < 3; ++b) dbeta += 2.0 * WENO_B[r][a][b] * q[b];
+            grad[2 - r + a] += omega * WENO_C[r][a] + (p[r] - W) / S * dalpha_dbeta * dbeta;
+        }
+    }
+}
+
+/* |lambda|'(u): sign(u) for Burgers (lambda = u); 0 for advection (constant lambda) */
+static double abs_lambda_deriv(const orc_scheme* s, double u)
+{
+    if (s->flux != 0) return 0.0;
+    return u > 0.0 ? 1.0 : (u < 0.0 ? -1.0 : 0.0);
+}
+
+static double flux_fprime(const orc_scheme* s, double u)
+{
+    if (s->flux == 0) return u;
+    return s->a;
+}
+
+/*
+ * out = J_A(u)^T v: the transpose of the Jacobian of the semi-discrete operator.
+ * Sum_i v_i A_i = sum_k F_{k+1/2} (v_{k+1} - v_k)/dx, so g_k = (v_{k+1} - v_k)/dx is
+ * the adjoint of F_{k+1/2}.  F depends on u^-_k, u^+_k and alpha_LF.  alpha_LF is a
+ * maximum; its subgradient puts all weight on the first (interface, side) attaining
+ * it, scanning k = 0..nx-1 and u^- before u^+.
+ */
+void orc_spatial_operator_vjp(const orc_scheme* s, const double* u, const double* v, double* out)
+{
+    int n = s->nx;
+    double dx = s->L / (double)n;
+    double* um = (double*)malloc(sizeof(double) * (size_t)n);
+    double* up = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        um[i] = recon_minus(s, u, i);
+        up[i] = recon_plus(s, u, i);
+        out[i] = 0.0;
+    }
+    double alpha;
+    int amax_k = -1, amax_side = 0;
+    if (s->alpha_fixed > 0.0) {
+        alpha = s->alpha_fixed;
+    } else {
+        alpha = 0.0;
+        for (int k = 0; k < n; ++k) {
+            double a1 = fabs(flux_lambda(s, um[k]));
+            if (a1 > alpha) { alpha = a1; amax_k = k; amax_side = 0; }
+            double a2 = fabs(flux_lambda(s, up[k]));
+            if (a2 > alpha) { alpha = a2; amax_k = k; amax_side = 1; }
+        }
+    }
+    double abar = 0.0;
+    for (int k = 0; k < n; ++k) {
+        double g = (v[wrap(k + 1, n)] - v[k]) / dx;
+        double gm = g * (0.5 * flux_fprime(s, um[k]) + 0.5 * alpha);
+        double gp = g * (0.5 * flux_fprime(s, up[k]) - 0.5 * alpha);
+        abar += g * (-0.5) * (up[k] - um[k]);
+        if (s->k == 0) {
+            out[k] += gm;
+            out[wrap(k + 1, n)] += gp;
+        } else {
+            double vv[5], gr[5];
+            for (int j = 0; j < 5; ++j) vv[j] = u[wrap(k - 2 + j, n)];
+            orc_weno5_left_grad(vv, s->eps, gr);
+            for (int j = 0; j < 5; ++j) out[wrap(k - 2 + j, n)] += gm * gr[j];
+            for (int j = 0; j < 5; ++j) vv[j] = u[wrap(k + 3 - j, n)];
+            orc_weno5_left_grad(vv, s->eps, gr);
+            for (int j = 0; j < 5; ++j) out[wrap(k + 3 - j, n)] += gp * gr[j];
+        }
+    }
+    if (amax_k >= 0) {
+        double uval = amax_side == 0 ? um[amax_k] : up[amax_k];
+        double c = abar * abs_lambda_deriv(s, uval);
+        if (c != 0.0) {
+            if (s->k == 0) {
+                out[amax_side == 0 ? amax_k : wrap(amax_k + 1, n)] += c;
+            } else {
+                double vv[5], gr[5];
+                for (int j = 0; j < 5; ++j)
+                    vv[j] = amax_side == 0 ? u[wrap(amax_k - 2 + j, n)] : u[wrap(amax_k + 3 - j, n)];
+                orc_weno5_left_grad(vv, s->eps, gr);
+                for (int j = 0; j < 5; ++j) {
+                    int cell = amax_side == 0 ? wrap(amax_k - 2 + j, n) : wrap(amax_k + 3 - j, n);
+                    out[cell] += c * gr[j];
+                }
+            }
+        }
+    }
+    free(um);
+    free(up);
+}
+
+/* lam_out = (dPhi/du (u))^T lam_in for one step of size dt: the stages of eq SSPRK1/2/3
+   in reverse order.  lam_out may alias lam_in. */
+void orc_phi_vjp(const orc_scheme* s, double dt, const double* u, const double* lam_in, double* lam_out)
+{
+    int n = s->nx;
+    size_t bytes = sizeof(double) * (size_t)n;
+    double* A = (double*)malloc(bytes);
+    double* u1 = (double*)malloc(bytes);
+    double* u2 = (double*)malloc(bytes);
+    double* l = (double*)malloc(bytes);
+    double* l1 = (double*)malloc(bytes);
+    double* l2 = (double*)malloc(bytes);
+    double* J = (double*)malloc(bytes);
+    memcpy(l, lam_in, bytes);
+    if (s->stepper == 1) {
+        /* y = u + dt A(u) */
+        orc_spatial_operator_vjp(s, u, l, J);
+        for (int i = 0; i < n; ++i) lam_out[i] = l[i] + dt * J[i];
+    } else if (s->stepper == 2) {
+        /* u1 = u + dt A(u); y = u/2 + u1/2 + dt/2 A(u1) */
+        orc_spatial_operator(s, u, A);
+        for (int i = 0; i < n; ++i) u1[i] = u[i] + dt * A[i];
+        orc_spatial_operator_vjp(s, u1, l, J);
+        for (int i = 0; i < n; ++i) l1[i] = 0.5 * l[i] + 0.5 * dt * J[i];
+        orc_spatial_operator_vjp(s, u, l1, J);
+        for (int i = 0; i < n; ++i) lam_out[i] = 0.5 * l[i] + l1[i] + dt * J[i];
+    } else {
+        /* u1 = u + dt A(u); u2 = 3u/4 + u1/4 + dt/4 A(u1); y = u/3 + 2u2/3 + 2dt/3 A(u2) */
+        orc_spatial_operator(s, u, A);
+        for (int i = 0; i < n; ++i) u1[i] = u[i] + dt * A[i];
+        orc_spatial_operator(s, u1, A);
+        for (int i = 0; i < n; ++i) u2[i] = 0.75 * u[i] + 0.25 * u1[i] + 0.25 * dt * A[i];
+        orc_spatial_operator_vjp(s, u2, l, J);
+        for (int i = 0; i < n; ++i) l2[i] = (2.0 / 3.0) * l[i] + (2.0 / 3.0) * dt * J[i];
+        orc_spatial_operator_vjp(s, u1, l2, J);
+        for (int i = 0; i < n; ++i) l1[i] = 0.25 * l2[i] + 0.25 * dt * J[i];
+        orc_spatial_operator_vjp(s, u, l1, J);
+        for (int i = 0; i < n; ++i)
+            lam_out[i] = (1.0 / 3.0) * l[i] + 0.75 * l2[i] + l1[i] + dt * J[i];
+    }
+    free(A);
+    free(u1);
+    free(u2);
+    free(l);
+    free(l1);
+    free(l2);
+    free(J);
+}
+
+/*
+ * Discrete adjoint of serial time stepping for J = 1/2 ||u^{nt} - u_target||^2:
+ * lambda^{nt} = u^{nt} - u_target; lambda^n = (dPhi/du(u^n))^T lambda^{n+1};
+ * grad = lambda^0 = dJ/du0.  Returns J.  The forward trajectory is kept whole.
+ */
+double orc_serial_adjoint(const orc_scheme* s, double dt, int32_t nt, const double* u0, const double* u_target,
+                          double* grad)
+{
+    int n = s->nx;
+    double* traj = (double*)malloc(sizeof(double) * (size_t)n * (size_t)(nt + 1));
+    orc_serial(s, dt, nt, u0, traj);
+    double J = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double d = traj[(size_t)nt * n + i] - u_target[i];
+        grad[i] = d;
+        J += 0.5 * d * d;
+    }
+    for (int32_t t = nt - 1; t >= 0; --t) orc_phi_vjp(s, dt, traj + (size_t)t * n, grad, grad);
+    free(traj);
+    return J;
+}

@@ -87,6 +87,11 @@ def lib():
         L.orc_mgrit.argtypes = [C.POINTER(Scheme), C.POINTER(Params), dp, dp, dp,
                                 C.POINTER(C.c_int32)]
         L.orc_mgrit.restype = C.c_int
+        L.orc_weno5_left_grad.argtypes = [dp, C.c_double, dp]
+        L.orc_spatial_operator_vjp.argtypes = [C.POINTER(Scheme), dp, dp, dp]
+        L.orc_phi_vjp.argtypes = [C.POINTER(Scheme), C.c_double, dp, dp, dp]
+        L.orc_serial_adjoint.argtypes = [C.POINTER(Scheme), C.c_double, C.c_int32, dp, dp, dp]
+        L.orc_serial_adjoint.restype = C.c_double
         _lib = L
     return _lib
 
@@ -161,3 +166,36 @@ def mgrit(s: Scheme, p: Params, u0, u_init=None):
     st = lib().orc_mgrit(C.byref(s), C.byref(p), _p(u0), _p(u), _p(hist), C.byref(iters))
     n = iters.value
     return u, hist[: n + 1] if p.levels > 1 else hist[:1], n, st
+
+
+def weno5_left_grad(v, eps=1e-6):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.zeros(5)
+    lib().orc_weno5_left_grad(_p(v), eps, _p(out))
+    return out
+
+
+def spatial_operator_vjp(s: Scheme, u, v):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.zeros_like(u)
+    lib().orc_spatial_operator_vjp(C.byref(s), _p(u), _p(v), _p(out))
+    return out
+
+
+def phi_vjp(s: Scheme, dt, u, lam):
+    """(dPhi/du(u))^T lam for one step."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    out = np.zeros_like(u)
+    lib().orc_phi_vjp(C.byref(s), dt, _p(u), _p(lam), _p(out))
+    return out
+
+
+def serial_adjoint(s: Scheme, dt, nt, u0, u_target):
+    """(J, dJ/du0) for J = 1/2 ||u(T) - u_target||^2 with serial time stepping."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    ut = np.ascontiguousarray(u_target, dtype=np.float64)
+    g = np.zeros_like(u0)
+    J = lib().orc_serial_adjoint(C.byref(s), dt, nt, _p(u0), _p(ut), _p(g))
+    return J, g
