@@ -193,6 +193,43 @@ size_t mgrit_workspace_bytes(const mgrit_scheme* s, const mgrit_params* p);
 int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, double* u,
                 void* workspace, size_t ws_bytes, double* res_hist, int32_t* iters, void* stream);
 
+/*
+ * Discrete adjoint (the derivative of Phi written by hand; not in the paper).
+ *
+ * mgrit_phi_vjp -- lam_out[b] = (dPhi/du(u[b]))^T lam_in[b] for independent
+ * lines: the Runge-Kutta stages of eq SSPRK1/2/3 in reverse, each applying the
+ * transpose of the Jacobian of A (eq spaceDisc, eq LFflux) including the
+ * subgradient of the global alpha_LF (all weight on the first maximising
+ * interface/side, interfaces in increasing order, u^- before u^+).  Arrays are
+ * nlines x nx.  The line must be a multiple of the cells per thread of the
+ * adjoint kernel (any nx <= 512, even nx <= 1024); else MGRIT_EUNSUPPORTED.
+ */
+int mgrit_phi_vjp(const mgrit_scheme* s, double dt, const double* u, const double* lam_in, double* lam_out,
+                  int64_t nlines, void* stream);
+
+/*
+ * mgrit_checkpoints -- serial forward stepping that keeps every `every`-th
+ * node: ckpt[i] = u^{i*every}, i = 0..nt/every (so ckpt[nt/every] = u(T)).
+ */
+int mgrit_checkpoints(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, const double* u0, double* ckpt,
+                      void* stream);
+
+/*
+ * mgrit_adjoint -- reverse sweep of serial time stepping from checkpoints:
+ * lambda_0 = (d u^{nt} / d u^0)^T lambda_T.  ckpt holds u at nodes 0, every,
+ * 2 every, ..., nt (mgrit_checkpoints, or the level-0 C-points of a converged
+ * mgrit_cycle with storage 1 and every = m).  Segments of `every` steps are
+ * recomputed `parallel_segments` at a time (in parallel, keeping every stage
+ * input), then swept backwards.  Memory: mgrit_adjoint_workspace_bytes =
+ * parallel_segments * every * stages * nx doubles plus one line.  For
+ * J = 1/2 ||u(T) - u_target||^2, lambda_T = u(T) - u_target and lambda_0 =
+ * dJ/du0.  lambda_0 may not alias lambda_T.
+ */
+size_t mgrit_adjoint_workspace_bytes(const mgrit_scheme* s, int32_t nt, int32_t every, int32_t parallel_segments);
+int mgrit_adjoint(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, int32_t parallel_segments,
+                  const double* ckpt, const double* lambda_T, double* lambda_0, void* workspace, size_t ws_bytes,
+                  void* stream);
+
 /* message of the last failure on this thread ("" if none) */
 const char* mgrit_last_error(void);
 
@@ -214,7 +251,9 @@ enum {
     MGRIT_KC_INTERP = 5,     /* injection + F-relaxation (ideal interpolation)   */
     MGRIT_KC_COARSE = 6,     /* serial solve on the coarsest level               */
     MGRIT_KC_AUX = 7,        /* norms, copies, flags                             */
-    MGRIT_KC_COUNT = 8
+    MGRIT_KC_ADJOINT = 8,    /* reverse sweeps / single-step VJPs                */
+    MGRIT_KC_ADJOINT_RECOMPUTE = 9, /* segment recomputation keeping stage inputs */
+    MGRIT_KC_COUNT = 10
 };
 
 typedef struct {

@@ -103,6 +103,21 @@ bool choose_cfg(int nx, int nlines, KernelCfg* out)
     return false;
 }
 
+// Adjoint configurations (no register spills): the line must be a multiple of
+// the cells per thread and fit one workgroup.
+const int kMaxAdjLine = 64 * 8 * 2;
+
+bool choose_adj_cfg(int nx, KernelCfg* out)
+{
+    static const KernelCfg pref[] = {{1, 1}, {1, 2}, {1, 4}, {1, 8}, {2, 4}, {2, 8}};
+    for (const KernelCfg& c : pref)
+        if (c.cpt * c.nw * 64 >= nx && nx % c.cpt == 0) {
+            *out = c;
+            return true;
+        }
+    return false;
+}
+
 // ---------------------------------------------------------------------------
 // validation
 // ---------------------------------------------------------------------------
@@ -182,6 +197,30 @@ int launch(int kc, const SweepArgs& a, const mgrit_scheme* s, hipStream_t st, do
     }
     hipError_t e = mgk::launch_sweep(a, cfg, s->k, s->stepper, st);
     if (e != hipSuccess) return hip_fail(e, "sweep kernel launch");
+    if (g_prof) {
+        HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
+        g_pending.push_back(pe);
+    }
+    return MGRIT_OK;
+}
+
+int launch_adj(int kc, const mgk::AdjArgs& a, const mgrit_scheme* s, int store_mode, hipStream_t st, double cells)
+{
+    KernelCfg cfg;
+    if (!choose_adj_cfg(s->nx, &cfg))
+        return fail(MGRIT_EUNSUPPORTED, "adjoint: nx = %d is not supported (at most %d cells, even above 512)", s->nx,
+                    kMaxAdjLine);
+    PendingEvent pe;
+    if (g_prof) {
+        pe.kc = kc;
+        pe.phi_lines = cells / (double)s->nx;
+        pe.cells = cells;
+        HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
+        HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
+        HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
+    }
+    hipError_t e = mgk::launch_adjoint(a, cfg, s->k, s->stepper, store_mode, st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
     if (g_prof) {
         HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
         g_pending.push_back(pe);
@@ -626,6 +665,124 @@ int mgrit_residual(const mgrit_scheme* s, double dt, int32_t m, const double* u,
     if (norm != nullptr) {
         rc = launch_aux([&] { return mgk::launch_sumsq_norm(r, (int64_t)nch * nx, norm, st); }, st);
         if (rc) return rc;
+    }
+    return MGRIT_OK;
+}
+
+int mgrit_phi_vjp(const mgrit_scheme* s, double dt, const double* u, const double* lam_in, double* lam_out,
+                  int64_t nlines, void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if ((rc = check_dt(dt))) return rc;
+    if (nlines < 0 || nlines > 2147483647LL) return fail(MGRIT_EINVAL, "nlines out of range");
+    if (nlines == 0) return MGRIT_OK;
+    if (u == nullptr || lam_in == nullptr || lam_out == nullptr) return fail(MGRIT_EINVAL, "NULL array");
+    mgk::AdjArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = s->nx;
+    a.nlines = (int)nlines;
+    a.nsteps = 1;
+    a.stored = 0;
+    a.dt = dt;
+    a.pc = phi_const(s);
+    a.u = u;
+    a.lam_in = lam_in;
+    a.lam_out = lam_out;
+    return launch_adj(MGRIT_KC_ADJOINT, a, s, 0, (hipStream_t)stream, (double)nlines * s->nx);
+}
+
+int mgrit_checkpoints(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, const double* u0, double* ckpt,
+                      void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if ((rc = check_dt(dt))) return rc;
+    if (nt < 1 || every < 1 || nt % every != 0) return fail(MGRIT_EINVAL, "nt must be a positive multiple of every");
+    if (u0 == nullptr || ckpt == nullptr) return fail(MGRIT_EINVAL, "NULL array");
+    SweepArgs a = base_args(s);
+    a.nchunks = 1;
+    a.nsteps = nt;
+    a.end_mode = mgk::END_NONE;
+    a.dt = dt;
+    a.ustart = u0;
+    a.ucommit = ckpt;
+    a.fout = ckpt;
+    a.fout_every = every;
+    return launch(MGRIT_KC_PHI, a, s, (hipStream_t)stream, (double)nt);
+}
+
+size_t mgrit_adjoint_workspace_bytes(const mgrit_scheme* s, int32_t nt, int32_t every, int32_t parallel_segments)
+{
+    if (check_scheme(s) != MGRIT_OK) return 0;
+    if (nt < 1 || every < 1 || nt % every != 0 || parallel_segments < 1) {
+        fail(MGRIT_EINVAL, "nt must be a positive multiple of every, parallel_segments >= 1");
+        return 0;
+    }
+    const int nseg = nt / every;
+    const int P = parallel_segments < nseg ? parallel_segments : nseg;
+    const size_t traj = sizeof(double) * (size_t)P * (size_t)every * (size_t)s->stepper * (size_t)s->nx;
+    return align256(traj) + align256(sizeof(double) * (size_t)s->nx);
+}
+
+int mgrit_adjoint(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, int32_t parallel_segments,
+                  const double* ckpt, const double* lambda_T, double* lambda_0, void* workspace, size_t ws_bytes,
+                  void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if ((rc = check_dt(dt))) return rc;
+    const size_t need = mgrit_adjoint_workspace_bytes(s, nt, every, parallel_segments);
+    if (need == 0) return MGRIT_EINVAL;
+    if (ckpt == nullptr || lambda_T == nullptr || lambda_0 == nullptr || workspace == nullptr)
+        return fail(MGRIT_EINVAL, "NULL array");
+    if (ws_bytes < need) return fail(MGRIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    if (((uintptr_t)workspace & 255) != 0) return fail(MGRIT_EINVAL, "workspace must be 256-byte aligned");
+    KernelCfg cfg;
+    if (!choose_adj_cfg(s->nx, &cfg))
+        return fail(MGRIT_EUNSUPPORTED, "adjoint: nx = %d is not supported", s->nx);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nx = s->nx;
+    const int nseg = nt / every;
+    const int P = parallel_segments < nseg ? parallel_segments : nseg;
+    const int ST = s->stepper;
+    double* traj = (double*)workspace;
+    double* lamw = (double*)((char*)workspace + align256(sizeof(double) * (size_t)P * every * ST * nx));
+    const int nbatch = (nseg + P - 1) / P;
+    const double* lam_cur = lambda_T;
+    int batch = 0;
+    for (int hi = nseg - 1; hi >= 0; hi -= P, ++batch) {
+        const int lo = hi - P + 1 > 0 ? hi - P + 1 : 0;
+        const int nb = hi - lo + 1;
+        // recompute the batch's segments in parallel, keeping every stage input
+        mgk::AdjArgs f;
+        std::memset(&f, 0, sizeof(f));
+        f.nx = s->nx;
+        f.nlines = nb;
+        f.nsteps = every;
+        f.dt = dt;
+        f.pc = phi_const(s);
+        f.u = ckpt + (int64_t)lo * nx;
+        f.u_stride = 1;
+        f.traj_out = traj;
+        f.traj_stride = (int64_t)every * ST * nx;
+        if ((rc = launch_adj(MGRIT_KC_ADJOINT_RECOMPUTE, f, s, 1, st, (double)nb * every * nx))) return rc;
+        // reverse sweep over the batch (one line, nb*every steps)
+        double* out = ((nbatch - 1 - batch) % 2 == 0) ? lambda_0 : lamw;
+        mgk::AdjArgs r;
+        std::memset(&r, 0, sizeof(r));
+        r.nx = s->nx;
+        r.nlines = 1;
+        r.nsteps = nb * every;
+        r.stored = 1;
+        r.dt = dt;
+        r.pc = phi_const(s);
+        r.traj = traj;
+        r.traj_stride = 0;
+        r.lam_in = lam_cur;
+        r.lam_out = out;
+        if ((rc = launch_adj(MGRIT_KC_ADJOINT, r, s, 0, st, (double)nb * every * nx))) return rc;
+        lam_cur = out;
     }
     return MGRIT_OK;
 }

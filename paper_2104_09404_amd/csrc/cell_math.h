@@ -86,6 +86,83 @@ MGK_HD void weno5_cell(double w0, double w1, double w2, double w3, double w4, do
     up = np * (dm * inv);
 }
 
+// Reverse mode of weno5_cell.  The forward intermediates (including the three
+// second-difference terms, from the window itself) are recomputed; adj(um, up,
+// um_bar, up_bar) receives the two reconstructions and returns their adjoints,
+// and the adjoint of the window w0..w4 is accumulated into wb[0..4].
+template <class Adj>
+MGK_HD void weno5_cell_vjp_f(double w0, double w1, double w2, double w3, double w4, double eps, Adj&& adj, double* wb)
+{
+    // forward
+    const double d2m = fma(-2.0, w1, w0 + w2);
+    const double d2c = fma(-2.0, w2, w1 + w3);
+    const double d2p = fma(-2.0, w3, w2 + w4);
+    const double Em = fma((13.0 / 12.0) * d2m, d2m, eps);
+    const double E0 = fma((13.0 / 12.0) * d2c, d2c, eps);
+    const double Ep = fma((13.0 / 12.0) * d2p, d2p, eps);
+    const double b = fma(1.5, w2, fma(-2.0, w1, 0.5 * w0));
+    const double d = 0.5 * (w3 - w1);
+    const double e = fma(1.5, w2, fma(-2.0, w3, 0.5 * w4));
+    const double tL = fma(b, b, Em), tC = fma(d, d, E0), tR = fma(e, e, Ep);
+    const double sL = tL * tL, sC = tC * tC, sR = tR * tR;
+    const double PLC = sL * sC, PLR = sL * sR, PCR = sC * sR;
+    const double h1 = 0.1 * w2, h5 = 0.5 * w2, h11 = (11.0 / 60.0) * w2;
+    const double cR = fma(-0.05, w4, fma(0.25, w3, h1));
+    const double cC = fma(0.2, w3, fma(-0.1, w1, h5));
+    const double cL = fma(2.0 / 60.0, w0, fma(-7.0 / 60.0, w1, h11));
+    const double dR = fma(2.0 / 60.0, w4, fma(-7.0 / 60.0, w3, h11));
+    const double dC = fma(0.2, w1, fma(-0.1, w3, h5));
+    const double dL = fma(-0.05, w0, fma(0.25, w1, h1));
+    const double nm = fma(PCR, cL, fma(PLR, cC, PLC * cR));
+    const double dm = fma(0.1, PCR, fma(0.6, PLR, 0.3 * PLC));
+    const double np = fma(PCR, dL, fma(PLR, dC, PLC * dR));
+    const double dp = fma(0.3, PCR, fma(0.6, PLR, 0.1 * PLC));
+    const double inv = recip(dm * dp);
+    const double idm = dp * inv, idp = dm * inv;  // 1/dm, 1/dp
+    const double um = nm * idm, up = np * idp;
+    double um_bar, up_bar;
+    adj(um, up, um_bar, up_bar);
+    // reverse: um = nm/dm, up = np/dp
+    const double nmb = um_bar * idm, dmb = -um_bar * um * idm;
+    const double npb = up_bar * idp, dpb = -up_bar * up * idp;
+    const double PLCb = fma(nmb, cR, fma(0.3, dmb, fma(npb, dR, 0.1 * dpb)));
+    const double PLRb = fma(nmb, cC, fma(0.6, dmb, fma(npb, dC, 0.6 * dpb)));
+    const double PCRb = fma(nmb, cL, fma(0.1, dmb, fma(npb, dL, 0.3 * dpb)));
+    const double cRb = nmb * PLC, cCb = nmb * PLR, cLb = nmb * PCR;
+    const double dRb = npb * PLC, dCb = npb * PLR, dLb = npb * PCR;
+    const double sLb = fma(PLCb, sC, PLRb * sR);
+    const double sCb = fma(PLCb, sL, PCRb * sR);
+    const double sRb = fma(PLRb, sL, PCRb * sC);
+    const double tLb = 2.0 * tL * sLb, tCb = 2.0 * tC * sCb, tRb = 2.0 * tR * sRb;
+    const double bb = 2.0 * b * tLb, db = 2.0 * d * tCb, eb = 2.0 * e * tRb;
+    // second differences: E = 13/12 d2^2 + eps, d2 = a - 2b + c
+    const double d2mb = (2.0 * 13.0 / 12.0) * d2m * tLb;
+    const double d2cb = (2.0 * 13.0 / 12.0) * d2c * tCb;
+    const double d2pb = (2.0 * 13.0 / 12.0) * d2p * tRb;
+    wb[0] += 0.5 * bb + (2.0 / 60.0) * cLb - 0.05 * dLb + d2mb;
+    wb[1] += -2.0 * bb - 0.5 * db - 0.1 * cCb - (7.0 / 60.0) * cLb + 0.2 * dCb + 0.25 * dLb - 2.0 * d2mb + d2cb;
+    wb[2] += 1.5 * bb + 1.5 * eb + 0.1 * cRb + 0.5 * cCb + (11.0 / 60.0) * (cLb + dRb) + 0.5 * dCb + 0.1 * dLb + d2mb -
+             2.0 * d2cb + d2pb;
+    wb[3] += 0.5 * db - 2.0 * eb + 0.25 * cRb + 0.2 * cCb - (7.0 / 60.0) * dRb - 0.1 * dCb + d2cb - 2.0 * d2pb;
+    wb[4] += 0.5 * eb - 0.05 * cRb + (2.0 / 60.0) * dRb + d2pb;
+}
+
+// Reverse mode of weno5_cell for given adjoints of the two reconstructions.
+MGK_HD void weno5_cell_vjp(double w0, double w1, double w2, double w3, double w4, double eps, double um_bar,
+                           double up_bar, double* wb)
+{
+    weno5_cell_vjp_f(
+        w0, w1, w2, w3, w4, eps,
+        [&](double, double, double& umb, double& upb) {
+            umb = um_bar;
+            upb = up_bar;
+        },
+        wb);
+}
+
+// f'(u) = 2 fa u + fb
+MGK_HD double flux_fprime(double u, double fa, double fb) { return fma(2.0 * fa, u, fb); }
+
 // f(u) = u (fa u + fb): Burgers (fa = 1/2, fb = 0) or advection (fa = 0, fb = a)
 MGK_HD double flux_f(double u, double fa, double fb) { return u * fma(fa, u, fb); }
 

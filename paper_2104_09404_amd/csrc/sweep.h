@@ -46,6 +46,7 @@ struct SweepArgs {
     double* ucommit;
     int64_t ucommit_stride;
     double* fout;
+    int fout_every;         // > 1: store only nodes n with n % fout_every == 0, at fout + (n/fout_every)*nx
     const double* g;
     double* side_out;
     const double* cref;     // current value of the chunk's end C-point: cref + (c+1)*cref_stride*nx
@@ -57,6 +58,23 @@ struct SweepArgs {
     double* uc_out;
     double* gc_out;
     const int* flag;        // if non-null and *flag != 0 the launch does nothing
+};
+
+// Adjoint launches (adjoint_impl.h): one workgroup per line b.
+struct AdjArgs {
+    int nx;
+    int nlines;
+    int nsteps;
+    int stored;             // stage inputs read from traj (else recomputed from u, nsteps == 1)
+    double dt;
+    PhiConst pc;
+    const double* u;        // start (stage_store) / state u^n (recompute) of line b at u + b*u_stride*nx
+    int64_t u_stride;
+    const double* traj;     // stage inputs of step n: traj + b*traj_stride + (n*ST + s)*nx
+    double* traj_out;       // the same layout, written by the stage-store kernel
+    int64_t traj_stride;
+    const double* lam_in;   // adjoint at the end of the stretch, line b at lam_in + b*nx
+    double* lam_out;        // adjoint at its start
 };
 
 struct KernelCfg {
@@ -86,12 +104,23 @@ struct KernelCfg {
     X(1, 16)            \
     X(2, 16)
 
+// (cells per thread, waves) pairs compiled for the adjoint; the line must be a
+// multiple of the cells per thread
+#define MGK_ADJ_CFG_LIST(X) \
+    X(1, 1)                 \
+    X(1, 2)                 \
+    X(1, 4)                 \
+    X(1, 8)                 \
+    X(2, 4)                 \
+    X(2, 8)
+
 inline size_t smem_bytes(int cpt, int nw)
 {
     return sizeof(double) * (64 * (size_t)nw * (size_t)cpt + 2 * 64 * (size_t)nw + 3 * (size_t)nw);
 }
 
 hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
+hipError_t launch_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int stepper, int store_mode, hipStream_t s);
 hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s);
 hipError_t launch_clear_ints(int* p, int n, hipStream_t s);
 hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_t s);

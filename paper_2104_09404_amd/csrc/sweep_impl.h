@@ -353,7 +353,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a)
     for (int j = 1; j <= a.nsteps; ++j) {
         phi<CPT, NW, K, ST, RAG>(x, a.dt, g, sm, a.pc, par);
         if (a.g != nullptr) add_line(x, a.g + (n0 + j) * nx, g);
-        if (a.fout != nullptr) store_line(x, a.fout + (n0 + j) * nx, g);
+        if (a.fout != nullptr) {
+            if (a.fout_every <= 1) store_line(x, a.fout + (n0 + j) * nx, g);
+            else if ((n0 + j) % a.fout_every == 0) store_line(x, a.fout + ((n0 + j) / a.fout_every) * nx, g);
+        }
     }
 
     if constexpr (END == END_NONE) return;

@@ -21,11 +21,12 @@ MGRIT_EHIP = -2
 MGRIT_EUNSUPPORTED = -4
 
 KERNEL_CLASSES = ["phi", "relax_fc_l0", "relax_fr_l0", "relax_fc_coarse", "relax_fr_coarse", "interp",
-                  "coarse_solve", "aux"]
+                  "coarse_solve", "aux", "adjoint", "adjoint_recompute"]
 
 EXPORTED = ["mgrit_phi", "mgrit_serial", "mgrit_relax", "mgrit_residual", "mgrit_workspace_bytes",
             "mgrit_cycle", "mgrit_last_error", "mgrit_set_profiling", "mgrit_get_profile",
-            "mgrit_kernel_config", "mgrit_set_kernel_config"]
+            "mgrit_kernel_config", "mgrit_set_kernel_config", "mgrit_phi_vjp", "mgrit_checkpoints",
+            "mgrit_adjoint_workspace_bytes", "mgrit_adjoint"]
 
 
 class MgritError(RuntimeError):
@@ -103,8 +104,14 @@ def load(path: str = LIB_PATH):
     L.mgrit_get_profile.argtypes = [C.POINTER(ProfileEntry), C.c_int]
     L.mgrit_kernel_config.argtypes = [i32, i32, C.POINTER(i32), C.POINTER(i32)]
     L.mgrit_set_kernel_config.argtypes = [i32, i32, i32, i32, i32]
+    L.mgrit_phi_vjp.argtypes = [S, C.c_double, dp, dp, dp, i64, vp]
+    L.mgrit_checkpoints.argtypes = [S, C.c_double, i32, i32, dp, dp, vp]
+    L.mgrit_adjoint_workspace_bytes.argtypes = [S, i32, i32, i32]
+    L.mgrit_adjoint_workspace_bytes.restype = C.c_size_t
+    L.mgrit_adjoint.argtypes = [S, C.c_double, i32, i32, i32, dp, dp, dp, vp, C.c_size_t, vp]
     for name in EXPORTED:
-        if name in ("mgrit_last_error", "mgrit_set_profiling", "mgrit_workspace_bytes"):
+        if name in ("mgrit_last_error", "mgrit_set_profiling", "mgrit_workspace_bytes",
+                    "mgrit_adjoint_workspace_bytes"):
             continue
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -225,3 +232,36 @@ def set_kernel_config(nx_lo: int, nx_hi: int, cpt: int, waves: int, latency: boo
 
 def clear_kernel_config():
     _check(load().mgrit_set_kernel_config(0, 0, 0, 0, 0))
+
+
+def phi_vjp(s: Scheme, dt: float, u, lam_in, lam_out, stream=None):
+    """lam_out[b] = (dPhi/du(u[b]))^T lam_in[b] for every line b."""
+    nlines = u.numel() // s.nx
+    _check(load().mgrit_phi_vjp(C.byref(s), dt, _ptr(u), _ptr(lam_in), _ptr(lam_out), nlines, _stream(stream)))
+
+
+def checkpoints(s: Scheme, dt: float, nt: int, every: int, u0, ckpt, stream=None):
+    """Serial forward keeping nodes 0, every, ..., nt in ckpt [(nt/every)+1, nx]."""
+    _check(load().mgrit_checkpoints(C.byref(s), dt, nt, every, _ptr(u0), _ptr(ckpt), _stream(stream)))
+
+
+def adjoint_workspace_bytes(s: Scheme, nt: int, every: int, parallel_segments: int) -> int:
+    n = load().mgrit_adjoint_workspace_bytes(C.byref(s), nt, every, parallel_segments)
+    if n == 0:
+        raise MgritError(MGRIT_EINVAL, load().mgrit_last_error().decode())
+    return n
+
+
+def adjoint(s: Scheme, dt: float, nt: int, every: int, ckpt, lambda_T, lambda_0, parallel_segments: int = 0,
+            workspace=None, stream=None):
+    """lambda_0 = (du^{nt}/du^0)^T lambda_T from checkpoints (reverse sweep on the GPU).
+    parallel_segments = 0 recomputes all segments in one launch."""
+    import torch
+
+    nseg = nt // every
+    P = parallel_segments if parallel_segments > 0 else nseg
+    if workspace is None:
+        nbytes = adjoint_workspace_bytes(s, nt, every, P)
+        workspace = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
+    _check(load().mgrit_adjoint(C.byref(s), dt, nt, every, P, _ptr(ckpt), _ptr(lambda_T), _ptr(lambda_0),
+                                C.c_void_p(workspace.data_ptr()), workspace.numel() * 8, _stream(stream)))

@@ -75,3 +75,9 @@ extern "C" void hk_phi(int nx, const double* u, int k, int stepper, double fa, d
     free(A);
     free(v);
 }
+
+extern "C" void hk_recon_vjp(const double* w, double eps, double umb, double upb, double* wb)
+{
+    for (int j = 0; j < 5; ++j) wb[j] = 0.0;
+    weno5_cell_vjp(w[0], w[1], w[2], w[3], w[4], eps, umb, upb, wb);
+}

@@ -27,6 +27,7 @@ def hk(tmp_path_factory):
     L.hk_operator.restype = C.c_double
     L.hk_phi.argtypes = [C.c_int, dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                          C.c_double, C.c_double, dp]
+    L.hk_recon_vjp.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp]
     return L
 
 
@@ -84,3 +85,21 @@ def test_step_matches_oracle(hk, orc, stepper, k):
         hk.hk_phi(nx, p(u), k, stepper, fa, fb, float(nx), 1e-6, 0.0, dt, p(out))
         ref = orc.phi(orc.scheme(nx, flux=flux, k=k, stepper=stepper, a=1.1), dt, u)
         assert np.linalg.norm(out - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_reconstruction_vjp_matches_oracle_gradient(hk, orc):
+    """Reverse mode of the kernel's reconstruction of a cell: with adjoint 1 on
+    u^- it is the oracle's gradient of W; with adjoint 1 on u^+ it is the
+    mirrored gradient of W on the mirrored window."""
+    g = np.random.default_rng(3)
+    windows = list(g.uniform(-1, 1, (100, 5))) + list(W.shock_lines(1, 20, 5))
+    for w in windows:
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        wb = np.zeros(5)
+        hk.hk_recon_vjp(p(w), 1e-6, 1.0, 0.0, p(wb))
+        ref = orc.weno5_left_grad(w, 1e-6)
+        assert np.max(np.abs(wb - ref)) <= 1e-9 * max(1.0, np.max(np.abs(ref))), (w, wb, ref)
+        wb = np.zeros(5)
+        hk.hk_recon_vjp(p(w), 1e-6, 0.0, 1.0, p(wb))
+        ref = orc.weno5_left_grad(np.ascontiguousarray(w[::-1]), 1e-6)[::-1]
+        assert np.max(np.abs(wb - ref)) <= 1e-9 * max(1.0, np.max(np.abs(ref))), (w, wb, ref)
