@@ -35,6 +35,43 @@ METRIC = "WENO5-SSPRK3 fine cell-steps/s in MGRIT relax; adjoint/forward time ra
 # divisions count as one flop
 FLOPS_PER_CELL_STEP = 440.0
 PEAK_FP64 = 78.6e12
+DOMINANT = "relax_fc_kernel<4, 4, 2, 3, false>"
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the FETCH_SIZE / WRITE_SIZE counter
+    record in profiles/traffic.json (counters scaled by a plain copy of known
+    size), or None when the record is missing or the kernel's sources changed
+    since the counters were taken."""
+    import hashlib
+
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            rec = json.load(f)[kernel]
+        h = hashlib.sha256()
+        for name in rec["sources"]:
+            with open(os.path.join(ROOT, name), "rb") as f:
+                h.update(f.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
+def gpu_serial_ms(mgrit, s, pb, u0, reps=3):
+    """Serial time stepping of the same problem on the GPU (N_T steps of Phi on
+    one line, one workgroup), the comparison point for the MGRIT solve."""
+    import torch
+
+    out = torch.empty((pb.nt + 1, pb.nx), dtype=torch.float64, device=u0.device)
+    mgrit.serial(s, pb.dt, pb.nt, u0, out)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        mgrit.serial(s, pb.dt, pb.nt, u0, out)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best * 1e3
 
 
 def parse():
@@ -75,8 +112,8 @@ def cpu_baseline(pb, budget_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the path shards in time across GPUs "
-              "by design, but no multi-GPU run is implemented); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the MGRIT sweeps would shard in time across "
+              "GPUs, but no multi-GPU path is implemented; use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -141,12 +178,13 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "fused level-0 F+C relaxation sweep (sweep_kernel, 512 chunks x 8 Phi steps)",
+            "kernel": DOMINANT + ": level-0 F-sweep + C-step + residual, 512 chunks x 8 Phi steps x 1024 cells",
             "achieved": achieved,
             "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved * 1e12 / PEAK_FP64,
-            "traffic": None,
+            "traffic": measured_traffic(DOMINANT),
+            "traffic_unit": "HBM bytes per launch",
             "flops_per_cell_step": FLOPS_PER_CELL_STEP,
             "avg_launch_ms": dom_ms,
         },
@@ -156,6 +194,7 @@ def main():
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
         "adjoint_forward_ratio": None,
         "mgrit_converges": bool(np.isfinite(hist[-1]) and hist[-1] < 1e-10),
+        "gpu_serial_ms": gpu_serial_ms(mgrit, s, pb, u0),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb, args.cpu_seconds)

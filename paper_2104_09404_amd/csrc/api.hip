@@ -228,6 +228,16 @@ int launch_adj(int kc, const mgk::AdjArgs& a, const mgrit_scheme* s, int store_m
     return MGRIT_OK;
 }
 
+// Two ints of pinned host memory per calling thread, allocated on the thread's
+// first mgrit_cycle and kept until the process ends: the stop flag and the
+// residual count are read back through it without a per-call allocation.
+int* pinned_flags()
+{
+    thread_local int* buf = nullptr;
+    if (!buf && hipHostMalloc((void**)&buf, sizeof(int) * 2, hipHostMallocDefault) != hipSuccess) buf = nullptr;
+    return buf;
+}
+
 template <class F>
 int launch_aux(F&& f, hipStream_t st)
 {
@@ -855,8 +865,8 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
     cy.flag = flag;
     const int nch0 = p->nt / p->m;
     int host_flag = 0;
-    int* pinned = nullptr;
-    HIP_TRY(hipHostMalloc((void**)&pinned, sizeof(int) * 2, hipHostMallocDefault), "hipHostMalloc");
+    int* pinned = pinned_flags();
+    if (!pinned) return fail(MGRIT_EHIP, "hipHostMalloc of the stop-flag buffer failed");
     int k = 0;
     for (;; ++k) {
         // first level-0 sweep of the next cycle: F-relaxation and the residual r_k
@@ -886,18 +896,15 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
         }
     }
     if (rc) {
-        (void)hipHostFree(pinned);
         return rc;
     }
     hipError_t e = hipMemcpyAsync(pinned, ints, sizeof(int) * 2, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
-        (void)hipHostFree(pinned);
         return hip_fail(e, "final readback");
     }
     host_flag = pinned[0];
     const int nres = pinned[1];
-    (void)hipHostFree(pinned);
     if (nres < 1 || nres > p->max_iter + 1) return fail(MGRIT_EHIP, "inconsistent residual counter %d", nres);
     HIP_TRY(hipMemcpy(res_hist, hist, sizeof(double) * (size_t)nres, hipMemcpyDeviceToHost), "hipMemcpy");
     *iters = nres - 1;
