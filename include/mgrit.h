@@ -10,7 +10,18 @@
  * Conventions shared by every entry point
  *   - All array pointers are DEVICE pointers to contiguous FP64 data owned by
  *     the caller (e.g. torch tensors).  The library never allocates or frees
- *     caller memory and allocates no device memory in any call below.
+ *     caller memory.  It allocates device memory only once per device: the
+ *     2.1 MB synchronisation buffer of split lines (below), on the first
+ *     split-line launch outside mgrit_cycle, kept until the process ends.
+ *   - Line length.  Lines of up to 4096 cells run on one workgroup each.
+ *     Longer lines (or any range chosen with mgrit_set_tiled_config) are split
+ *     into tiles of balanced length, one workgroup per tile, which meet once
+ *     per Runge-Kutta stage through a global counter; their launches are
+ *     cooperative (all workgroups of a line resident at once).  Results are
+ *     bitwise the same as with one workgroup per line.  Split-line calls
+ *     outside mgrit_cycle that overlap in time on one device (different
+ *     streams or threads) share that device's synchronisation buffer and must
+ *     not run concurrently.
  *   - A "line" is N_x consecutive doubles (one spatial grid function).  A
  *     level array holds lines for nodes 0..N, node n at offset n*N_x: the
  *     space-time iterate is stored time-major, contiguous in x.
@@ -271,6 +282,18 @@ int mgrit_get_profile(mgrit_profile_entry* out, int cap);
    fewer than 256 lines count as latency bound and get more threads per line.
    Returns MGRIT_EUNSUPPORTED if no compiled configuration covers the line. */
 int mgrit_kernel_config(int32_t nx, int32_t nlines, int32_t* cells_per_thread, int32_t* waves);
+
+/* split-line configuration for lines of nx cells: cells per thread, waves
+   per tile and number of tiles; *tiles == 1 (and zeros) when the line runs on
+   one workgroup. */
+int mgrit_tiled_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves, int32_t* tiles);
+
+/* split lines of nx_lo..nx_hi cells into tiles of at most
+   64 * waves * cells_per_thread cells (balanced lengths), with a compiled
+   split-line pair: (1,4), (2,4), (2,8), (4,4), (4,8), (4,16).
+   cells_per_thread == 0 clears every such setting.  Lines must give tiles of
+   at least 3 cells.  Not thread safe. */
+int mgrit_set_tiled_config(int32_t nx_lo, int32_t nx_hi, int32_t cells_per_thread, int32_t waves);
 
 /* override the configuration for line lengths nx_lo..nx_hi in latency-bound
    (latency != 0) or throughput launches (used by the autotuner); the pair must

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -103,6 +104,89 @@ bool choose_cfg(int nx, int nlines, KernelCfg* out)
     return false;
 }
 
+// ---------------------------------------------------------------------------
+// tiled lines (several workgroups per line): lines longer than one workgroup
+// holds, or any range set by mgrit_set_tiled_config
+// ---------------------------------------------------------------------------
+const KernelCfg kTiledCfgs[] = {
+#define MGK_ENTRY(C, W) {C, W},
+    MGK_TILED_CFG_LIST(MGK_ENTRY)
+#undef MGK_ENTRY
+};
+
+struct TiledOverride {
+    int nx_lo, nx_hi;
+    KernelCfg cfg;
+};
+std::vector<TiledOverride> g_tiled_overrides;
+
+bool tiled_compiled(int cpt, int nw)
+{
+    for (const KernelCfg& c : kTiledCfgs)
+        if (c.cpt == cpt && c.nw == nw) return true;
+    return false;
+}
+
+int tiles_for(int nx, const KernelCfg& c)
+{
+    const int T = 64 * c.nw * c.cpt;
+    return (nx + T - 1) / T;
+}
+
+// Configuration and number of tiles for lines of nx cells, or false when a
+// line of nx cells runs in one workgroup.  Default: 4096-cell tiles of 4
+// cells per thread when the line splits into whole threads, else 2048-cell
+// tiles (4 cells per thread, 8 waves), which keep the ragged variant free
+// of register spills.
+// Longest split line: 256 tiles of 4096 cells (one per compute unit), or 512
+// tiles of 2048 cells (two per compute unit).
+const int kMaxTiledLine = 1 << 20;
+
+bool choose_tiled(int nx, KernelCfg* out, int* tiles)
+{
+    if (nx > kMaxTiledLine) return false;
+    for (const TiledOverride& o : g_tiled_overrides)
+        if (nx >= o.nx_lo && nx <= o.nx_hi) {
+            *out = o.cfg;
+            *tiles = tiles_for(nx, o.cfg);
+            return nx / *tiles >= 3;
+        }
+    if (nx <= kMaxLine) return false;
+    const KernelCfg big{4, 16};
+    const int G = tiles_for(nx, big);
+    if (nx % G == 0 && (nx / G) % 4 == 0) {
+        *out = big;
+        *tiles = G;
+        return true;
+    }
+    *out = KernelCfg{4, 8};
+    *tiles = tiles_for(nx, *out);
+    return true;
+}
+
+// Synchronisation scratch of tiled launches: mgrit_cycle takes it from its
+// workspace (set for the duration of the call on the calling thread); the
+// other entry points use one buffer per device, allocated on the first tiled
+// launch on that device and kept until the process ends.
+thread_local char* tl_tile_scratch = nullptr;
+std::mutex g_tile_mutex;
+std::vector<char*> g_tile_scratch;
+
+int device_tile_scratch(char** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_tile_mutex);
+    if ((int)g_tile_scratch.size() <= dev) g_tile_scratch.resize(dev + 1, nullptr);
+    if (g_tile_scratch[dev] == nullptr) {
+        void* p = nullptr;
+        HIP_TRY(hipMalloc(&p, mgk::tile_scratch_bytes()), "hipMalloc of the tiled-line scratch");
+        g_tile_scratch[dev] = (char*)p;
+    }
+    *out = g_tile_scratch[dev];
+    return MGRIT_OK;
+}
+
 // Adjoint configurations (no register spills): the line must be a multiple of
 // the cells per thread and fit one workgroup.
 const int kMaxAdjLine = 64 * 8 * 2;
@@ -133,8 +217,9 @@ int check_scheme(const mgrit_scheme* s)
     if (s->flux == 1 && !std::isfinite(s->a)) return fail(MGRIT_EINVAL, "advection speed must be finite");
     if (!(s->alpha_fixed >= 0.0) || !std::isfinite(s->alpha_fixed)) return fail(MGRIT_EINVAL, "alpha_fixed must be >= 0");
     KernelCfg c;
-    if (!choose_cfg(s->nx, kLatencyLines, &c))
-        return fail(MGRIT_EUNSUPPORTED, "nx = %d exceeds the largest one-workgroup line (%d cells)", s->nx, kMaxLine);
+    int tiles = 0;
+    if (!choose_tiled(s->nx, &c, &tiles) && !choose_cfg(s->nx, kLatencyLines, &c))
+        return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", s->nx);
     return MGRIT_OK;
 }
 
@@ -181,11 +266,24 @@ bool g_prof = false;
 mgrit_profile_entry g_prof_acc[MGRIT_KC_COUNT];
 std::vector<PendingEvent> g_pending;
 
-int launch(int kc, const SweepArgs& a, const mgrit_scheme* s, hipStream_t st, double phi_lines)
+int launch(int kc, const SweepArgs& a0, const mgrit_scheme* s, hipStream_t st, double phi_lines)
 {
     KernelCfg cfg;
-    if (!choose_cfg(s->nx, a.nchunks, &cfg))
+    int tiles = 0;
+    SweepArgs a = a0;
+    const bool tiled = choose_tiled(s->nx, &cfg, &tiles);
+    if (tiled) {
+        char* scratch = tl_tile_scratch;
+        if (scratch == nullptr) {
+            int rc = device_tile_scratch(&scratch);
+            if (rc) return rc;
+        }
+        a.tiles = tiles;
+        a.tile_sync = (unsigned long long*)scratch;
+        a.tile_pub = (double*)(scratch + sizeof(unsigned long long) * (size_t)(mgk::kTileMaxWorkgroups + 1));
+    } else if (!choose_cfg(s->nx, a.nchunks, &cfg)) {
         return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", s->nx);
+    }
     PendingEvent pe;
     if (g_prof) {
         pe.kc = kc;
@@ -195,8 +293,9 @@ int launch(int kc, const SweepArgs& a, const mgrit_scheme* s, hipStream_t st, do
         HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
         HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
     }
-    hipError_t e = mgk::launch_sweep(a, cfg, s->k, s->stepper, st);
-    if (e != hipSuccess) return hip_fail(e, "sweep kernel launch");
+    hipError_t e = tiled ? mgk::launch_tiled(a, cfg, s->k, s->stepper, st)
+                         : mgk::launch_sweep(a, cfg, s->k, s->stepper, st);
+    if (e != hipSuccess) return hip_fail(e, tiled ? "tiled sweep kernel launch" : "sweep kernel launch");
     if (g_prof) {
         HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
         g_pending.push_back(pe);
@@ -285,7 +384,8 @@ struct Layout {
     int N[16];          // steps per level
     size_t u_off[16];   // level arrays, l >= 1 (bytes)
     size_t g_off[16];
-    size_t side_off, partial_off, hist_off, ints_off, total;
+    size_t side_off, partial_off, hist_off, ints_off, tile_off, total;
+    int tiles;          // workgroups per line (1: one workgroup per line)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -335,14 +435,19 @@ Layout make_layout(const mgrit_scheme* s, const mgrit_params* p)
         if (l + 1 < ly.L) N /= p->m;
     }
     const int nch0 = (ly.L > 1) ? p->nt / p->m : 1;
+    KernelCfg tc;
+    int tiles = 0;
+    ly.tiles = choose_tiled(s->nx, &tc, &tiles) ? tiles : 1;
     ly.side_off = off;
     off = align256(off + line * (size_t)(nch0 + 1));
     ly.partial_off = off;
-    off = align256(off + sizeof(double) * (size_t)nch0);
+    off = align256(off + sizeof(double) * (size_t)nch0 * (size_t)ly.tiles);
     ly.hist_off = off;
     off = align256(off + sizeof(double) * (size_t)(p->max_iter + 2));
     ly.ints_off = off;
     off = align256(off + 4 * sizeof(int));
+    ly.tile_off = off;
+    if (ly.tiles > 1) off = align256(off + mgk::tile_scratch_bytes());
     ly.total = off;
     return ly;
 }
@@ -529,6 +634,32 @@ int mgrit_kernel_config(int32_t nx, int32_t nlines, int32_t* cells_per_thread, i
     if (!choose_cfg(nx, nlines, &c)) return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", nx);
     if (cells_per_thread) *cells_per_thread = c.cpt;
     if (waves) *waves = c.nw;
+    return MGRIT_OK;
+}
+
+int mgrit_tiled_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves, int32_t* tiles)
+{
+    KernelCfg c{0, 0};
+    int G = 1;
+    if (!choose_tiled(nx, &c, &G)) {
+        c = KernelCfg{0, 0};
+        G = 1;
+    }
+    if (cells_per_thread) *cells_per_thread = c.cpt;
+    if (waves) *waves = c.nw;
+    if (tiles) *tiles = G;
+    return MGRIT_OK;
+}
+
+int mgrit_set_tiled_config(int32_t nx_lo, int32_t nx_hi, int32_t cpt, int32_t waves)
+{
+    if (cpt == 0) {
+        g_tiled_overrides.clear();
+        return MGRIT_OK;
+    }
+    if (!tiled_compiled(cpt, waves)) return fail(MGRIT_EINVAL, "tiled configuration (%d, %d) is not compiled", cpt, waves);
+    if (nx_lo > nx_hi || nx_lo < 8) return fail(MGRIT_EINVAL, "empty range or nx_lo < 8");
+    g_tiled_overrides.insert(g_tiled_overrides.begin(), TiledOverride{nx_lo, nx_hi, KernelCfg{cpt, waves}});
     return MGRIT_OK;
 }
 
@@ -835,6 +966,20 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
     int* counter = ints + 1;
     double* hist = (double*)(cy.ws + cy.ly.hist_off);
     hipStream_t st = cy.st;
+    // tiled launches of this call synchronise through the workspace
+    struct ScratchScope {
+        explicit ScratchScope(char* p) { tl_tile_scratch = p; }
+        ~ScratchScope() { tl_tile_scratch = nullptr; }
+    } scope(cy.ly.tiles > 1 ? cy.ws + cy.ly.tile_off : nullptr);
+    // a tiled line whose workgroups failed to meet (cannot happen with the
+    // cooperative launch; the kernels' spins are bounded) leaves its error word set
+    auto tile_error = [&]() -> int {
+        if (cy.ly.tiles <= 1) return MGRIT_OK;
+        unsigned long long w = 0;
+        HIP_TRY(hipMemcpy(&w, cy.ws + cy.ly.tile_off, sizeof(w), hipMemcpyDeviceToHost), "hipMemcpy");
+        if (w != 0) return fail(MGRIT_EHIP, "tiled sweep: workgroups of a line failed to synchronise");
+        return MGRIT_OK;
+    };
 
     // initial iterate
     const int64_t nlines0 = (p->storage == 0) ? (int64_t)p->nt + 1 : (int64_t)(p->nt / p->m) + 1;
@@ -857,6 +1002,7 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
         a.fout = u;
         if ((rc = launch(MGRIT_KC_COARSE, a, s, st, (double)p->nt))) return rc;
         HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if ((rc = tile_error())) return rc;
         res_hist[0] = 0.0;
         *iters = 1;
         return MGRIT_OK;
@@ -873,7 +1019,7 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
         if (p->relax == 1) rc = cy.sweep_fc(0, true);
         else rc = cy.sweep_fr(0, false, true);
         if (rc) break;
-        rc = launch_aux([&] { return mgk::launch_reduce_norm(cy.partial(), nch0, hist, counter, flag, p->tol, st); }, st);
+        rc = launch_aux([&] { return mgk::launch_reduce_norm(cy.partial(), nch0 * cy.ly.tiles, hist, counter, flag, p->tol, st); }, st);
         if (rc) break;
         if (k == p->max_iter) break;
         // rest of the cycle
@@ -907,6 +1053,7 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
     const int nres = pinned[1];
     if (nres < 1 || nres > p->max_iter + 1) return fail(MGRIT_EHIP, "inconsistent residual counter %d", nres);
     HIP_TRY(hipMemcpy(res_hist, hist, sizeof(double) * (size_t)nres, hipMemcpyDeviceToHost), "hipMemcpy");
+    if ((rc = tile_error())) return rc;
     *iters = nres - 1;
     return host_flag ? MGRIT_OK : MGRIT_NOT_CONVERGED;
 }

@@ -39,6 +39,21 @@ hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int ste
     return launch_sweep_ks<2, 3>(a, cfg, s);
 }
 
+template <int K, int ST>
+hipError_t launch_tiled_ks(const SweepArgs& a, const KernelCfg& cfg, hipStream_t s);
+
+hipError_t launch_tiled(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
+{
+    if (a.nchunks <= 0) return hipSuccess;
+    if (k == 0) {
+        if (stepper == 1) return launch_tiled_ks<0, 1>(a, cfg, s);
+        if (stepper == 2) return launch_tiled_ks<0, 2>(a, cfg, s);
+        return launch_tiled_ks<0, 3>(a, cfg, s);
+    }
+    if (stepper == 1) return launch_tiled_ks<2, 1>(a, cfg, s);
+    if (stepper == 2) return launch_tiled_ks<2, 2>(a, cfg, s);
+    return launch_tiled_ks<2, 3>(a, cfg, s);
+}
 
 // dst[b] = src for b < nlines (fill every node with the initial condition)
 __global__ void broadcast_kernel(const double* src, double* dst, int64_t nx, int64_t nlines)

@@ -58,7 +58,22 @@ struct SweepArgs {
     double* uc_out;
     double* gc_out;
     const int* flag;        // if non-null and *flag != 0 the launch does nothing
+    // lines split over several workgroups (tiled_impl.h)
+    int tiles;              // workgroups per line (0: one workgroup per line)
+    int groups;             // line groups resident at once (set by the launcher)
+    unsigned long long* tile_sync;  // [0] error word, [1 + group] arrival counters
+    double* tile_pub;       // published edge data: groups x tiles x 2 x kTileSlot
 };
+
+// tiled lines: doubles per published slot, and the largest resident grid the
+// synchronisation scratch is sized for
+constexpr int kTileSlot = 16;
+constexpr int kTileMaxWorkgroups = 8192;
+inline size_t tile_scratch_bytes()
+{
+    return sizeof(unsigned long long) * (size_t)(kTileMaxWorkgroups + 1) +
+           sizeof(double) * (size_t)kTileMaxWorkgroups * 2 * kTileSlot;
+}
 
 // Adjoint launches (adjoint_impl.h): one workgroup per line b.
 struct AdjArgs {
@@ -114,12 +129,28 @@ struct KernelCfg {
     X(2, 4)                 \
     X(2, 8)
 
+// (cells per thread, waves) pairs compiled for tiled lines; a tile holds at
+// most 64 * waves * cells per thread cells
+#define MGK_TILED_CFG_LIST(X) \
+    X(1, 4)                   \
+    X(2, 4)                   \
+    X(2, 8)                   \
+    X(4, 4)                   \
+    X(4, 8)                   \
+    X(4, 16)
+
+inline size_t tiled_smem_bytes(int cpt, int nw)
+{
+    return sizeof(double) * (64 * (size_t)nw * (size_t)cpt + 6 + 2 * 64 * (size_t)nw + (size_t)nw + 40);
+}
+
 inline size_t smem_bytes(int cpt, int nw)
 {
     return sizeof(double) * (64 * (size_t)nw * (size_t)cpt + 2 * 64 * (size_t)nw + 3 * (size_t)nw);
 }
 
 hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
+hipError_t launch_tiled(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int stepper, int store_mode, hipStream_t s);
 hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s);
 hipError_t launch_clear_ints(int* p, int n, hipStream_t s);

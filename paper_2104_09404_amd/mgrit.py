@@ -26,7 +26,7 @@ KERNEL_CLASSES = ["phi", "relax_fc_l0", "relax_fr_l0", "relax_fc_coarse", "relax
 EXPORTED = ["mgrit_phi", "mgrit_serial", "mgrit_relax", "mgrit_residual", "mgrit_workspace_bytes",
             "mgrit_cycle", "mgrit_last_error", "mgrit_set_profiling", "mgrit_get_profile",
             "mgrit_kernel_config", "mgrit_set_kernel_config", "mgrit_phi_vjp", "mgrit_checkpoints",
-            "mgrit_adjoint_workspace_bytes", "mgrit_adjoint"]
+            "mgrit_adjoint_workspace_bytes", "mgrit_adjoint", "mgrit_tiled_config", "mgrit_set_tiled_config"]
 
 
 class MgritError(RuntimeError):
@@ -232,6 +232,23 @@ def set_kernel_config(nx_lo: int, nx_hi: int, cpt: int, waves: int, latency: boo
 
 def clear_kernel_config():
     _check(load().mgrit_set_kernel_config(0, 0, 0, 0, 0))
+
+
+def tiled_config(nx: int):
+    """(cells per thread, waves, tiles) of split lines of nx cells; tiles == 1
+    when a line runs on one workgroup."""
+    c, w, t = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    _check(load().mgrit_tiled_config(nx, C.byref(c), C.byref(w), C.byref(t)))
+    return c.value, w.value, t.value
+
+
+def set_tiled_config(nx_lo: int, nx_hi: int, cpt: int, waves: int):
+    """Split lines of nx_lo..nx_hi cells into tiles of at most 64*waves*cpt cells."""
+    _check(load().mgrit_set_tiled_config(nx_lo, nx_hi, cpt, waves))
+
+
+def clear_tiled_config():
+    _check(load().mgrit_set_tiled_config(0, 0, 0, 0))
 
 
 def phi_vjp(s: Scheme, dt: float, u, lam_in, lam_out, stream=None):

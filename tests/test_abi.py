@@ -67,7 +67,7 @@ def test_validation_errors_without_gpu(lib):
     assert lib.mgrit_phi(C.byref(s), -1.0, None, None, 1, None) == mgrit.MGRIT_EINVAL
     assert lib.mgrit_phi(C.byref(s), 1e-3, None, None, 0, None) == mgrit.MGRIT_OK  # empty input
     assert lib.mgrit_phi(C.byref(s), 1e-3, None, None, 3, None) == mgrit.MGRIT_EINVAL
-    big = mgrit.scheme(1 << 20)
+    big = mgrit.scheme((1 << 20) + 2)
     assert lib.mgrit_phi(C.byref(big), 1e-3, None, None, 1, None) == mgrit.MGRIT_EUNSUPPORTED
     p = mgrit.params(100, 1e-3, 8, 3)  # 100 not divisible by 64
     assert lib.mgrit_workspace_bytes(C.byref(s), C.byref(p)) == 0
@@ -96,3 +96,31 @@ def test_kernel_config_choice(lib):
     mgrit.set_kernel_config(1024, 1024, 8, 4)
     assert mgrit.kernel_config(1024, 512) == (8, 4)
     mgrit.clear_kernel_config()
+
+
+def test_split_line_choice(lib):
+    """Lines up to 4096 cells run on one workgroup; longer ones are split into
+    balanced tiles: 4096-cell tiles when they divide into whole threads of 4
+    cells, else tiles of at most 2048 cells."""
+    from paper_2104_09404_amd import mgrit
+
+    assert mgrit.tiled_config(4096) == (0, 0, 1)
+    assert mgrit.tiled_config(65536) == (4, 16, 16)
+    assert mgrit.tiled_config(8192) == (4, 16, 2)
+    assert mgrit.tiled_config(6002) == (4, 8, 3)
+    assert mgrit.tiled_config(1 << 20) == (4, 16, 256)
+    assert mgrit.tiled_config((1 << 20) + 2) == (0, 0, 1)
+    mgrit.set_tiled_config(300, 1000, 1, 4)
+    assert mgrit.tiled_config(1000) == (1, 4, 4)
+    assert mgrit.tiled_config(300) == (1, 4, 2)
+    with pytest.raises(mgrit.MgritError):
+        mgrit.set_tiled_config(100, 200, 8, 8)  # not compiled as a split-line pair
+    mgrit.clear_tiled_config()
+    assert mgrit.tiled_config(1000) == (0, 0, 1)
+    # the workspace of a split-line problem holds the synchronisation scratch
+    s = mgrit.scheme(8192)
+    p = mgrit.params(256, 1e-4, 8, 2)
+    n_split = lib.mgrit_workspace_bytes(C.byref(s), C.byref(p))
+    s2 = mgrit.scheme(4096)
+    n_one = lib.mgrit_workspace_bytes(C.byref(s2), C.byref(p))
+    assert n_split > 2 * n_one
