@@ -11,7 +11,7 @@
  *   - All array pointers are DEVICE pointers to contiguous FP64 data owned by
  *     the caller (e.g. torch tensors).  The library never allocates or frees
  *     caller memory.  It allocates device memory only once per device: the
- *     2.1 MB synchronisation buffer of split lines (below), on the first
+ *     3.1 MB synchronisation buffer of split lines (below), on the first
  *     split-line launch outside mgrit_cycle, kept until the process ends.
  *   - Line length.  Lines of up to 4096 cells run on one workgroup each.
  *     Longer lines (or any range chosen with mgrit_set_tiled_config) are split

@@ -280,7 +280,7 @@ int launch(int kc, const SweepArgs& a0, const mgrit_scheme* s, hipStream_t st, d
         }
         a.tiles = tiles;
         a.tile_sync = (unsigned long long*)scratch;
-        a.tile_pub = (double*)(scratch + sizeof(unsigned long long) * (size_t)(mgk::kTileMaxWorkgroups + 1));
+        a.tile_pub = (double*)(scratch + mgk::tile_sync_bytes());
     } else if (!choose_cfg(s->nx, a.nchunks, &cfg)) {
         return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", s->nx);
     }

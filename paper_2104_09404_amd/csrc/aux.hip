@@ -80,7 +80,7 @@ __global__ void sumsq_norm_kernel(const double* r, int64_t n, double* out)
 
 __global__ void clear_ints_kernel(int* p, int n)
 {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // norm of the residual from per-chunk partial sums, in a fixed order; records
@@ -124,7 +124,9 @@ hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_
 
 hipError_t launch_clear_ints(int* p, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(clear_ints_kernel, dim3(1), dim3(64), 0, s, p, n);
+    if (n <= 0) return hipSuccess;
+    const int blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+    hipLaunchKernelGGL(clear_ints_kernel, dim3(blocks), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -61,18 +61,23 @@ struct SweepArgs {
     // lines split over several workgroups (tiled_impl.h)
     int tiles;              // workgroups per line (0: one workgroup per line)
     int groups;             // line groups resident at once (set by the launcher)
-    unsigned long long* tile_sync;  // [0] error word, [1 + group] arrival counters
+    unsigned long long* tile_sync;  // [0] error word, [kTileCounterStride * (1 + group)] arrival counters
     double* tile_pub;       // published edge data: groups x tiles x 2 x kTileSlot
 };
 
-// tiled lines: doubles per published slot, and the largest resident grid the
-// synchronisation scratch is sized for
+// tiled lines: doubles per published slot, words between arrival counters
+// (one 128-byte line each, so that groups do not contend for a line), and the
+// largest resident grid the synchronisation scratch is sized for
 constexpr int kTileSlot = 16;
+constexpr int kTileCounterStride = 16;
 constexpr int kTileMaxWorkgroups = 8192;
+inline size_t tile_sync_bytes()
+{
+    return sizeof(unsigned long long) * kTileCounterStride * (size_t)(kTileMaxWorkgroups + 1);
+}
 inline size_t tile_scratch_bytes()
 {
-    return sizeof(unsigned long long) * (size_t)(kTileMaxWorkgroups + 1) +
-           sizeof(double) * (size_t)kTileMaxWorkgroups * 2 * kTileSlot;
+    return tile_sync_bytes() + sizeof(double) * (size_t)kTileMaxWorkgroups * 2 * kTileSlot;
 }
 
 // Adjoint launches (adjoint_impl.h): one workgroup per line b.

@@ -15,8 +15,8 @@
 //      and publishes its local max |u^{+-}| and (Fa, Fb) of the three
 //      interfaces inside each edge to a global slot;
 //   4. meets the other tiles of the line at a global counter (one arrival per
-//      publishing thread, bounded spin), reads alpha_LF = max over all tiles
-//      (eq eigs) and its neighbours' edge data;
+//      tile, bounded spin), reads alpha_LF = max over all tiles (eq eigs) and
+//      its neighbours' edge data;
 //   5. updates its cells and, with the neighbours' data, its six ghost cells,
 //      evaluating exactly the operations the owners evaluate on the same
 //      operands, so ghosts stay bitwise equal to the owners' cells.
@@ -262,15 +262,23 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
     ts.ep += 1;
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
+        // lanes 0..12 publish the slot with device-coherent stores; waiting for
+        // their completion before the arrival orders them before it for any
+        // reader that sees the arrival (readers use device-coherent loads), so
+        // no cache write-back or invalidation of the whole L2 is needed
+        if (lane < 13) {
+            double v;
+            if (lane == 0) {
+                v = sm.amax[0];
+#pragma unroll
+                for (int w2 = 1; w2 < NW; ++w2) v = fmax(v, sm.amax[w2]);
+            } else {
+                v = sm.misc[16 + lane];
+            }
+            __hip_atomic_store(ts.slot(ts.tile, parity) + lane, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
         if (lane == 0) {
-            double* mine = ts.slot(ts.tile, parity);
-            double mx = sm.amax[0];
-#pragma unroll
-            for (int w2 = 1; w2 < NW; ++w2) mx = fmax(mx, sm.amax[w2]);
-            mine[0] = mx;
-#pragma unroll
-            for (int i = 0; i < 12; ++i) mine[1 + i] = sm.misc[17 + i];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_fetch_add(ts.cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned long long target = (unsigned long long)ts.G * (unsigned long long)ts.ep;
             long long spins = 0;
@@ -282,11 +290,10 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
                     bad = 1.0;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_s_sleep(2);
             }
             sm.misc[39] = bad;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         double mx = 0.0;
         for (int i = lane; i < ts.G; i += 64) mx = fmax(mx, load_agent(ts.slot(i, parity)));
         mx = wave_max(mx);
@@ -522,7 +529,7 @@ __device__ __forceinline__ void tiled_body(const SweepArgs& a)
     g.init(a.nx, tile, G);
     TSync ts;
     ts.err = a.tile_sync;
-    ts.cnt = a.tile_sync + 1 + grp;
+    ts.cnt = a.tile_sync + kTileCounterStride * (1 + grp);
     ts.pub = a.tile_pub + (int64_t)grp * G * 2 * kTileSlot;
     ts.G = G;
     ts.tile = tile;
@@ -576,7 +583,7 @@ static hipError_t launch_coop(Fn fn, const SweepArgs& a, int nw, size_t shmem, h
     if (G < 1 || cap < G) return hipErrorCooperativeLaunchTooLarge;
     SweepArgs b = a;
     b.groups = (int)std::min((long long)a.nchunks, cap / G);
-    e = launch_clear_ints((int*)b.tile_sync, 2 * (b.groups + 1), s);
+    e = launch_clear_ints((int*)b.tile_sync, 2 * kTileCounterStride * (b.groups + 1), s);
     if (e != hipSuccess) return e;
     void* args[] = {(void*)&b};
     return hipLaunchCooperativeKernel((const void*)fn, dim3((unsigned)(b.groups * G)), dim3(64 * nw), args,

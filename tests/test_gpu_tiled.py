@@ -165,6 +165,47 @@ def test_cycle_split_is_bitwise(orc, tiled, relax, cycle):
     assert np.all(rel_lines(ub, uo) < TOL)
 
 
+def test_many_line_groups_twice(tiled):
+    """512 chunks of 1024 cells on 2 tiles each, so that hundreds of line
+    groups are resident at once, launched twice in a row (every group's
+    counter must start from zero at every launch): F- and FCF-relaxation
+    bitwise equal to one workgroup per line."""
+    nx, m, n = 1024, 8, 4096
+    u = W.random_lines(70, n + 1, nx)
+    s = tiled.scheme(nx)
+    dt = 0.8 / nx / np.max(np.abs(u))
+    for kind in (0, 2):
+        ref = T(u)
+        tiled.relax(s, dt, m, kind, ref, None, n)
+        ref = H(ref)
+        tiled.set_tiled_config(nx, nx, 2, 4)
+        for _ in range(2):
+            got = T(u)
+            tiled.relax(s, dt, m, kind, got, None, n)
+            assert np.array_equal(H(got), ref)
+        tiled.clear_tiled_config()
+
+
+def test_benchmark_cycle_split_is_bitwise(tiled):
+    """Two V-cycles of the 1024-cell benchmark workload with every sweep on
+    split lines equal the one-workgroup cycles bitwise."""
+    pb = W.w1_burgers_weno5()
+    s = tiled.scheme_from_problem(pb)
+    p = tiled.params(pb.nt, pb.dt, pb.m, pb.levels, relax=1, max_iter=2, tol=-1.0)
+
+    def run():
+        ug = T(np.zeros((pb.nt + 1, pb.nx)))
+        tiled.cycle(s, p, T(pb.u0), ug)
+        return H(ug)
+
+    a = run()
+    tiled.set_tiled_config(pb.nx, pb.nx, 4, 4)
+    b = run()
+    with np.errstate(invalid="ignore"):
+        same = (a == b) | (np.isnan(a) & np.isnan(b))
+    assert np.all(same)
+
+
 # ---------------------------------------------------------------------------
 # lines longer than one workgroup holds (default split)
 # ---------------------------------------------------------------------------
