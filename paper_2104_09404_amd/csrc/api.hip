@@ -202,6 +202,48 @@ bool choose_adj_cfg(int nx, KernelCfg* out)
     return false;
 }
 
+// Adjoint of split lines: a split-line setting (mgrit_set_tiled_config) whose
+// pair is compiled for the adjoint applies to it too; otherwise lines that no
+// single-workgroup adjoint configuration covers use tiles of at most 512
+// cells, one cell per thread.
+const KernelCfg kTiledAdjCfgs[] = {
+#define MGK_ENTRY(C, W) {C, W},
+    MGK_TADJ_CFG_LIST(MGK_ENTRY)
+#undef MGK_ENTRY
+};
+
+bool tiled_adj_ok(int nx, const KernelCfg& c, int G)
+{
+    if (G < 1 || nx / G < 6) return false;
+    if (c.cpt > 1 && (nx % G != 0 || (nx / G) % c.cpt != 0)) return false;
+    return (nx + G - 1) / G <= 64 * c.nw * c.cpt;
+}
+
+bool choose_tiled_adj(int nx, KernelCfg* out, int* tiles)
+{
+    if (nx > kMaxTiledLine) return false;
+    for (const TiledOverride& o : g_tiled_overrides)
+        if (nx >= o.nx_lo && nx <= o.nx_hi) {
+            for (const KernelCfg& c : kTiledAdjCfgs)
+                if (c.cpt == o.cfg.cpt && c.nw == o.cfg.nw) {
+                    const int G = tiles_for(nx, c);
+                    if (!tiled_adj_ok(nx, c, G)) return false;
+                    *out = c;
+                    *tiles = G;
+                    return true;
+                }
+            break;
+        }
+    KernelCfg single;
+    if (choose_adj_cfg(nx, &single)) return false;
+    const KernelCfg c{1, 8};
+    const int G = tiles_for(nx, c);
+    if (!tiled_adj_ok(nx, c, G)) return false;
+    *out = c;
+    *tiles = G;
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // validation
 // ---------------------------------------------------------------------------
@@ -815,6 +857,11 @@ int mgrit_phi_vjp(const mgrit_scheme* s, double dt, const double* u, const doubl
 {
     int rc = check_scheme(s);
     if (rc) return rc;
+    {
+        KernelCfg c;
+        if (!choose_adj_cfg(s->nx, &c))
+            return fail(MGRIT_EUNSUPPORTED, "mgrit_phi_vjp: nx = %d needs a split line; use mgrit_adjoint", s->nx);
+    }
     if ((rc = check_dt(dt))) return rc;
     if (nlines < 0 || nlines > 2147483647LL) return fail(MGRIT_EINVAL, "nlines out of range");
     if (nlines == 0) return MGRIT_OK;
@@ -863,7 +910,11 @@ size_t mgrit_adjoint_workspace_bytes(const mgrit_scheme* s, int32_t nt, int32_t 
     const int nseg = nt / every;
     const int P = parallel_segments < nseg ? parallel_segments : nseg;
     const size_t traj = sizeof(double) * (size_t)P * (size_t)every * (size_t)s->stepper * (size_t)s->nx;
-    return align256(traj) + align256(sizeof(double) * (size_t)s->nx);
+    KernelCfg c;
+    int tiles = 0;
+    size_t tile = 0;
+    if (choose_tiled_adj(s->nx, &c, &tiles) || choose_tiled(s->nx, &c, &tiles)) tile = align256(mgk::tile_scratch_bytes());
+    return align256(traj) + align256(sizeof(double) * (size_t)s->nx) + tile;
 }
 
 int mgrit_adjoint(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, int32_t parallel_segments,
@@ -880,7 +931,9 @@ int mgrit_adjoint(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, i
     if (ws_bytes < need) return fail(MGRIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
     if (((uintptr_t)workspace & 255) != 0) return fail(MGRIT_EINVAL, "workspace must be 256-byte aligned");
     KernelCfg cfg;
-    if (!choose_adj_cfg(s->nx, &cfg))
+    int tiles = 0;
+    const bool split = choose_tiled_adj(s->nx, &cfg, &tiles);
+    if (!split && !choose_adj_cfg(s->nx, &cfg))
         return fail(MGRIT_EUNSUPPORTED, "adjoint: nx = %d is not supported", s->nx);
     hipStream_t st = (hipStream_t)stream;
     const int64_t nx = s->nx;
@@ -888,7 +941,40 @@ int mgrit_adjoint(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, i
     const int P = parallel_segments < nseg ? parallel_segments : nseg;
     const int ST = s->stepper;
     double* traj = (double*)workspace;
-    double* lamw = (double*)((char*)workspace + align256(sizeof(double) * (size_t)P * every * ST * nx));
+    const size_t traj_bytes = align256(sizeof(double) * (size_t)P * every * ST * nx);
+    double* lamw = (double*)((char*)workspace + traj_bytes);
+    char* tscratch = (char*)workspace + traj_bytes + align256(sizeof(double) * (size_t)nx);
+    // the forward recompute of split lines (split for the forward sweep) and
+    // the split reverse sweep synchronise through the workspace
+    struct ScratchScope {
+        explicit ScratchScope(char* p) { tl_tile_scratch = p; }
+        ~ScratchScope() { tl_tile_scratch = nullptr; }
+    } scope(split ? tscratch : nullptr);
+    auto tile_args = [&](mgk::AdjArgs& a) {
+        a.tiles = tiles;
+        a.tile_sync = (unsigned long long*)tscratch;
+        a.tile_pub = (double*)(tscratch + mgk::tile_sync_bytes());
+    };
+    auto run = [&](int kc, mgk::AdjArgs& a, int store_mode, double cells) -> int {
+        if (!split) return launch_adj(kc, a, s, store_mode, st, cells);
+        tile_args(a);
+        PendingEvent pe;
+        if (g_prof) {
+            pe.kc = kc;
+            pe.phi_lines = cells / (double)nx;
+            pe.cells = cells;
+            HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
+            HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
+            HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
+        }
+        hipError_t e = mgk::launch_tiled_adjoint(a, cfg, s->k, s->stepper, store_mode, st);
+        if (e != hipSuccess) return hip_fail(e, "split-line adjoint kernel launch");
+        if (g_prof) {
+            HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
+            g_pending.push_back(pe);
+        }
+        return MGRIT_OK;
+    };
     const int nbatch = (nseg + P - 1) / P;
     const double* lam_cur = lambda_T;
     int batch = 0;
@@ -907,7 +993,7 @@ int mgrit_adjoint(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, i
         f.u_stride = 1;
         f.traj_out = traj;
         f.traj_stride = (int64_t)every * ST * nx;
-        if ((rc = launch_adj(MGRIT_KC_ADJOINT_RECOMPUTE, f, s, 1, st, (double)nb * every * nx))) return rc;
+        if ((rc = run(MGRIT_KC_ADJOINT_RECOMPUTE, f, 1, (double)nb * every * nx))) return rc;
         // reverse sweep over the batch (one line, nb*every steps)
         double* out = ((nbatch - 1 - batch) % 2 == 0) ? lambda_0 : lamw;
         mgk::AdjArgs r;
@@ -922,8 +1008,14 @@ int mgrit_adjoint(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, i
         r.traj_stride = 0;
         r.lam_in = lam_cur;
         r.lam_out = out;
-        if ((rc = launch_adj(MGRIT_KC_ADJOINT, r, s, 0, st, (double)nb * every * nx))) return rc;
+        if ((rc = run(MGRIT_KC_ADJOINT, r, 0, (double)nb * every * nx))) return rc;
         lam_cur = out;
+    }
+    if (split) {
+        unsigned long long w = 0;
+        HIP_TRY(hipMemcpyAsync(&w, tscratch, sizeof(w), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        if (w != 0) return fail(MGRIT_EHIP, "split-line adjoint: workgroups of a line failed to synchronise");
     }
     return MGRIT_OK;
 }

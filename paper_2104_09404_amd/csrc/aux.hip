@@ -42,6 +42,23 @@ hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int ste
 template <int K, int ST>
 hipError_t launch_tiled_ks(const SweepArgs& a, const KernelCfg& cfg, hipStream_t s);
 
+template <int K, int ST>
+hipError_t launch_tiled_adjoint_ks(const AdjArgs& a, const KernelCfg& cfg, int store_mode, hipStream_t s);
+
+hipError_t launch_tiled_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int stepper, int store_mode,
+                                hipStream_t s)
+{
+    if (a.nlines <= 0) return hipSuccess;
+    if (k == 0) {
+        if (stepper == 1) return launch_tiled_adjoint_ks<0, 1>(a, cfg, store_mode, s);
+        if (stepper == 2) return launch_tiled_adjoint_ks<0, 2>(a, cfg, store_mode, s);
+        return launch_tiled_adjoint_ks<0, 3>(a, cfg, store_mode, s);
+    }
+    if (stepper == 1) return launch_tiled_adjoint_ks<2, 1>(a, cfg, store_mode, s);
+    if (stepper == 2) return launch_tiled_adjoint_ks<2, 2>(a, cfg, store_mode, s);
+    return launch_tiled_adjoint_ks<2, 3>(a, cfg, store_mode, s);
+}
+
 hipError_t launch_tiled(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
 {
     if (a.nchunks <= 0) return hipSuccess;

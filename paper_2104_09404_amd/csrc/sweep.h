@@ -95,6 +95,11 @@ struct AdjArgs {
     int64_t traj_stride;
     const double* lam_in;   // adjoint at the end of the stretch, line b at lam_in + b*nx
     double* lam_out;        // adjoint at its start
+    // lines split over several workgroups (tiled_adjoint_impl.h), as in SweepArgs
+    int tiles;
+    int groups;
+    unsigned long long* tile_sync;
+    double* tile_pub;
 };
 
 struct KernelCfg {
@@ -144,6 +149,14 @@ struct KernelCfg {
     X(4, 8)                   \
     X(4, 16)
 
+// (cells per thread, waves) pairs compiled for the adjoint of split lines;
+// every tile must be a whole number of threads
+#define MGK_TADJ_CFG_LIST(X) \
+    X(1, 4)                  \
+    X(2, 4)                  \
+    X(1, 8)                  \
+    X(2, 8)
+
 inline size_t tiled_smem_bytes(int cpt, int nw)
 {
     return sizeof(double) * (64 * (size_t)nw * (size_t)cpt + 6 + 2 * 64 * (size_t)nw + (size_t)nw + 40);
@@ -157,6 +170,8 @@ inline size_t smem_bytes(int cpt, int nw)
 hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
 hipError_t launch_tiled(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int stepper, int store_mode, hipStream_t s);
+hipError_t launch_tiled_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int stepper, int store_mode,
+                                hipStream_t s);
 hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s);
 hipError_t launch_clear_ints(int* p, int n, hipStream_t s);
 hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_t s);

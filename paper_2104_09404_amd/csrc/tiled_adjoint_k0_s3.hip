@@ -1,0 +1,8 @@
+// Adjoint kernels of split lines for reconstruction degree k = 0 and the
+// 3-stage Runge-Kutta scheme (one translation unit per scheme).
+#include "tiled_adjoint_impl.h"
+
+namespace mgk {
+template hipError_t launch_tiled_adjoint_ks<0, 3>(const AdjArgs& a, const KernelCfg& cfg, int store_mode,
+                                                          hipStream_t s);
+}  // namespace mgk
