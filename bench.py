@@ -109,6 +109,53 @@ def cpu_baseline(pb, budget_s):
                       % (reps, pb.nx, el)}
 
 
+def adjoint_ratio(mgrit, reps=3):
+    """Adjoint workload (Burgers WENO5 + SSPRK3, N_x = 4096, N_T = 2048, CFL 0.8,
+    checkpoints every 32 steps): time of the reverse sweep including the
+    recomputation of every segment (all 64 segments recomputed in one launch)
+    over the time of the forward it differentiates (serial stepping keeping the
+    checkpoints).  The 3-level MGRIT forward of this workload does not converge
+    (coarse CFL 6.4 / 51), so the serial forward is the denominator."""
+    import torch
+
+    from paper_2104_09404_amd import workloads as W
+
+    pb = W.w4_adjoint()
+    nx, nt, every = pb.nx, pb.nt, pb.extra["checkpoint_every"]
+    s = mgrit.scheme_from_problem(pb)
+    u0 = torch.from_numpy(pb.u0).cuda()
+    tgt = torch.from_numpy(pb.extra["u_target"]).cuda()
+    ck = torch.zeros((nt // every + 1, nx), dtype=torch.float64, device="cuda")
+    lam0 = torch.zeros(nx, dtype=torch.float64, device="cuda")
+    P = nt // every
+    ws = torch.empty(mgrit.adjoint_workspace_bytes(s, nt, every, P) // 8 + 64, dtype=torch.float64, device="cuda")
+
+    def fwd():
+        mgrit.checkpoints(s, pb.dt, nt, every, u0, ck)
+
+    def rev():
+        mgrit.adjoint(s, pb.dt, nt, every, ck, lamT, lam0, parallel_segments=P, workspace=ws)
+
+    def best(f):
+        f()
+        torch.cuda.synchronize()
+        b = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            b = min(b, time.perf_counter() - t0)
+        return b * 1e3
+
+    t_fwd = best(fwd)
+    lamT = (ck[-1] - tgt).contiguous()
+    t_rev = best(rev)
+    return {"value": t_rev / t_fwd, "adjoint_ms": t_rev, "forward_ms": t_fwd,
+            "workload": "adjoint_nx4096: Burgers WENO5 + SSPRK3, N_x=4096, N_T=2048, CFL 0.8, "
+                        "checkpoints every 32 steps, J = 1/2 ||u(T) - u_target||^2",
+            "forward": "serial stepping keeping the checkpoints (the MGRIT forward does not converge here)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -192,7 +239,7 @@ def main():
         "level0_relax_cell_steps_per_s": (prof["relax_fc_l0"]["cell_steps"] + prof["relax_fr_l0"]["cell_steps"])
         / ((prof["relax_fc_l0"]["ms"] + prof["relax_fr_l0"]["ms"]) * 1e-3),
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": adjoint_ratio(mgrit),
         "mgrit_converges": bool(np.isfinite(hist[-1]) and hist[-1] < 1e-10),
         "gpu_serial_ms": gpu_serial_ms(mgrit, s, pb, u0),
     }

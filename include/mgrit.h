@@ -302,6 +302,48 @@ int mgrit_set_tiled_config(int32_t nx_lo, int32_t nx_hi, int32_t cells_per_threa
 int mgrit_set_kernel_config(int32_t nx_lo, int32_t nx_hi, int32_t latency, int32_t cells_per_thread,
                             int32_t waves);
 
+/*
+ * Batches of independent problems (many initial-value problems solved by
+ * MGRIT together; not in the paper).  Every problem has its own scheme
+ * constants (flux, advection speed, nx, eps, L, alpha_fixed), fine step count
+ * and step; k and stepper are common.  The MGRIT settings (m, levels >= 2,
+ * relax, cycle, max_iter, init, coarse_guess, storage, sync_every, tol) are
+ * common; the nt and dt fields of the params are ignored.
+ *   u0   device, nx doubles: the problem's initial condition;
+ *   u    device, the problem's level-0 iterate, (nt+1) x nx (storage 0) or
+ *        (nt/m+1) x nx (storage 1), as for mgrit_cycle.
+ * One launch per phase of the cycle covers the chunks of every problem that
+ * shares a kernel configuration (lines longer than 4096 cells run their own
+ * split-line launches).  Each problem stops doing work once its residual
+ * norm is below tol (its chunks retire); the call returns when every
+ * problem has converged or after max_iter cycles.  Every problem's iterates
+ * are bitwise those of mgrit_cycle on that problem alone.
+ */
+typedef struct {
+    mgrit_scheme scheme;
+    int32_t nt;
+    int32_t pad_;
+    double dt;
+    const double* u0;
+    double* u;
+} mgrit_problem;
+
+/* workspace bytes of mgrit_cycle_batched (0 on invalid input) */
+size_t mgrit_batched_workspace_bytes(const mgrit_problem* probs, int32_t count, const mgrit_params* p);
+
+/*
+ * mgrit_cycle_batched -- FAS-MGRIT on `count` problems (host array probs).
+ * workspace: device, >= mgrit_batched_workspace_bytes, 256-byte aligned.
+ * res_hist: host, count x (max_iter+1) doubles: problem i's residual norms
+ * r_0 .. r_{iters[i]} at res_hist[i*(max_iter+1) + k], zeros after;
+ * iters: host, count (cycles applied to each problem); status: host, count
+ * (MGRIT_OK: converged, MGRIT_NOT_CONVERGED).  Synchronises the stream every
+ * sync_every cycles and at the end.  Returns MGRIT_OK unless an error
+ * occurred (per-problem convergence is in status).
+ */
+int mgrit_cycle_batched(const mgrit_problem* probs, int32_t count, const mgrit_params* p, void* workspace,
+                        size_t ws_bytes, double* res_hist, int32_t* iters, int32_t* status, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

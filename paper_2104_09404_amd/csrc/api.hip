@@ -2,6 +2,7 @@
 // configuration choice, workspace layout and the MGRIT cycle driver.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -308,8 +309,20 @@ bool g_prof = false;
 mgrit_profile_entry g_prof_acc[MGRIT_KC_COUNT];
 std::vector<PendingEvent> g_pending;
 
+// A batch records the sweeps of one cycle per problem instead of launching them
+struct Recorded {
+    int kc;
+    SweepArgs a;
+    double phi_lines;
+};
+thread_local std::vector<Recorded>* tl_recorder = nullptr;
+
 int launch(int kc, const SweepArgs& a0, const mgrit_scheme* s, hipStream_t st, double phi_lines)
 {
+    if (tl_recorder != nullptr) {
+        tl_recorder->push_back(Recorded{kc, a0, phi_lines});
+        return MGRIT_OK;
+    }
     KernelCfg cfg;
     int tiles = 0;
     SweepArgs a = a0;
@@ -1148,6 +1161,343 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
     if ((rc = tile_error())) return rc;
     *iters = nres - 1;
     return host_flag ? MGRIT_OK : MGRIT_NOT_CONVERGED;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches of independent problems
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchBucket {
+    KernelCfg cfg;
+    int ragged;
+    std::vector<int> probs;  // problem indices
+    std::vector<int> offset;
+    int nblocks;
+    size_t dev_off;          // offset / problem arrays in the workspace
+};
+
+struct BatchPhase {
+    int kc;
+    int end_mode;
+    size_t args_off;                 // count SweepArgs in the workspace
+    std::vector<BatchBucket> buckets;
+    std::vector<int> split;          // problems on split lines (own launches)
+    double cells;                    // cell steps of the phase over the batch
+};
+
+struct BatchPlan {
+    int count;
+    std::vector<Layout> ly;
+    std::vector<size_t> ly_off;      // per-problem workspace base
+    std::vector<BatchPhase> phA, phB;
+    size_t norm_off, conv_off, tile_off, tables_off, total;
+    bool any_split;
+    std::vector<SweepArgs> host_args;  // [phase][problem], A phases first
+    std::vector<double> host_phi;      // Phi applications of each entry of host_args
+    std::vector<int> host_ints;        // bucket offset / problem arrays
+    std::vector<mgk::BatchNorm> host_norm;
+};
+
+mgrit_params problem_params(const mgrit_params* p, const mgrit_problem* q)
+{
+    mgrit_params pp = *p;
+    pp.nt = q->nt;
+    pp.dt = q->dt;
+    return pp;
+}
+
+int check_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p)
+{
+    if (probs == nullptr || p == nullptr) return fail(MGRIT_EINVAL, "NULL problem table or params");
+    if (count < 1) return fail(MGRIT_EINVAL, "count must be >= 1");
+    if (p->levels < 2) return fail(MGRIT_EINVAL, "a batch needs levels >= 2");
+    for (int i = 0; i < count; ++i) {
+        const mgrit_problem& q = probs[i];
+        int rc = check_scheme(&q.scheme);
+        if (rc) return fail(rc, "problem %d: %s", i, mgrit_last_error());
+        const mgrit_params pp = problem_params(p, &q);
+        if ((rc = check_params(&q.scheme, &pp))) return fail(rc, "problem %d: %s", i, mgrit_last_error());
+        if (q.scheme.k != probs[0].scheme.k || q.scheme.stepper != probs[0].scheme.stepper)
+            return fail(MGRIT_EINVAL, "problem %d: every problem of a batch needs the same k and stepper", i);
+    }
+    return MGRIT_OK;
+}
+
+// Record the sweeps of one cycle of every problem, group them into buckets and
+// lay out the workspace.  With ws == nullptr only the sizes are computed.
+int plan_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p, char* ws, BatchPlan* bp)
+{
+    bp->count = count;
+    bp->ly.resize(count);
+    bp->ly_off.resize(count);
+    bp->any_split = false;
+    size_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        const mgrit_params pp = problem_params(p, &probs[i]);
+        bp->ly[i] = make_layout(&probs[i].scheme, &pp);
+        bp->ly_off[i] = off;
+        off = align256(off + bp->ly[i].total);
+        KernelCfg c;
+        int t = 0;
+        if (choose_tiled(probs[i].scheme.nx, &c, &t)) bp->any_split = true;
+    }
+    bp->norm_off = off;
+    off = align256(off + sizeof(mgk::BatchNorm) * (size_t)count);
+    bp->conv_off = off;
+    off = align256(off + 256);
+    bp->tile_off = off;
+    if (bp->any_split) off = align256(off + mgk::tile_scratch_bytes());
+    // record one cycle per problem
+    std::vector<std::vector<Recorded>> recA(count), recB(count);
+    for (int i = 0; i < count; ++i) {
+        const mgrit_problem& q = probs[i];
+        const mgrit_params pp = problem_params(p, &q);
+        Cycle cy;
+        cy.s = &q.scheme;
+        cy.p = &pp;
+        cy.ly = bp->ly[i];
+        cy.ws = (ws != nullptr ? ws : (char*)nullptr) + bp->ly_off[i];
+        cy.u0_level = q.u;
+        cy.st = nullptr;
+        const int L = pp.levels;
+        cy.cstride0 = (pp.storage == 0) ? pp.m : 1;
+        cy.fstore0 = pp.storage == 0;
+        double dtl = pp.dt;
+        for (int l = 0; l < L; ++l) {
+            cy.dtl[l] = dtl;
+            dtl *= (double)pp.m;
+        }
+        cy.flag = (int*)(cy.ws + cy.ly.ints_off);
+        int rc;
+        tl_recorder = &recA[i];
+        rc = (pp.relax == 1) ? cy.sweep_fc(0, true) : cy.sweep_fr(0, false, true);
+        tl_recorder = &recB[i];
+        if (!rc && pp.relax == 1) rc = cy.sweep_fr(0, true, false);
+        if (!rc) rc = (pp.cycle == 1) ? cy.fcycle(1) : cy.vcycle(1);
+        if (!rc) rc = cy.interp(0, false);
+        tl_recorder = nullptr;
+        if (rc) return rc;
+        if (recA[i].size() != recA[0].size() || recB[i].size() != recB[0].size())
+            return fail(MGRIT_EINVAL, "problem %d: cycle structure differs", i);
+    }
+    // phases and buckets
+    const size_t nA = recA[0].size(), nB = recB[0].size();
+    bp->host_args.assign((nA + nB) * (size_t)count, SweepArgs());
+    bp->host_phi.assign((nA + nB) * (size_t)count, 0.0);
+    bp->host_ints.clear();
+    size_t args_off = 0;  // relative to tables_off
+    auto build = [&](std::vector<std::vector<Recorded>>& rec, size_t nph, size_t base, std::vector<BatchPhase>& out) -> int {
+        out.resize(nph);
+        for (size_t ph = 0; ph < nph; ++ph) {
+            BatchPhase& P = out[ph];
+            P.kc = rec[0][ph].kc;
+            P.end_mode = rec[0][ph].a.end_mode;
+            P.args_off = args_off;
+            args_off += sizeof(SweepArgs) * (size_t)count;
+            P.cells = 0.0;
+            long long total_lines = 0;
+            for (int i = 0; i < count; ++i) total_lines += rec[i][ph].a.nchunks;
+            for (int i = 0; i < count; ++i) {
+                const Recorded& r = rec[i][ph];
+                bp->host_args[(base + ph) * count + i] = r.a;
+                bp->host_phi[(base + ph) * count + i] = r.phi_lines;
+                P.cells += r.phi_lines * (double)probs[i].scheme.nx;
+                KernelCfg c;
+                int t = 0;
+                if (choose_tiled(probs[i].scheme.nx, &c, &t)) {
+                    P.split.push_back(i);
+                    continue;
+                }
+                // serial solves (one chunk per problem) take the latency configuration
+                const int nl = (r.a.nchunks == 1) ? 1 : (int)std::min<long long>(total_lines, 1 << 30);
+                if (!choose_cfg(probs[i].scheme.nx, nl, &c))
+                    return fail(MGRIT_EUNSUPPORTED, "problem %d: no kernel configuration", i);
+                const int rag = (c.cpt > 1 && probs[i].scheme.nx % c.cpt != 0) ? 1 : 0;
+                BatchBucket* bk = nullptr;
+                for (BatchBucket& b : P.buckets)
+                    if (b.cfg.cpt == c.cpt && b.cfg.nw == c.nw && b.ragged == rag) bk = &b;
+                if (bk == nullptr) {
+                    P.buckets.push_back(BatchBucket{c, rag, {}, {}, 0, 0});
+                    bk = &P.buckets.back();
+                }
+                bk->offset.push_back(bk->nblocks);
+                bk->probs.push_back(i);
+                bk->nblocks += r.a.nchunks;
+            }
+            for (BatchBucket& b : P.buckets) {
+                b.dev_off = sizeof(int) * bp->host_ints.size();
+                bp->host_ints.insert(bp->host_ints.end(), b.offset.begin(), b.offset.end());
+                bp->host_ints.insert(bp->host_ints.end(), b.probs.begin(), b.probs.end());
+            }
+        }
+        return MGRIT_OK;
+    };
+    int rc = build(recA, nA, 0, bp->phA);
+    if (!rc) rc = build(recB, nB, nA, bp->phB);
+    if (rc) return rc;
+    bp->tables_off = off;
+    const size_t ints_rel = align256(args_off);
+    off = align256(off + ints_rel + sizeof(int) * bp->host_ints.size());
+    bp->total = off;
+    // fix the int-array offsets (relative to tables_off)
+    for (auto* v : {&bp->phA, &bp->phB})
+        for (BatchPhase& P : *v)
+            for (BatchBucket& b : P.buckets) b.dev_off += ints_rel;
+    // residual reduction table
+    bp->host_norm.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const Layout& l = bp->ly[i];
+        char* base = (ws != nullptr ? ws : (char*)nullptr) + bp->ly_off[i];
+        mgk::BatchNorm& e = bp->host_norm[i];
+        e.partial = (const double*)(base + l.partial_off);
+        e.n = (probs[i].nt / p->m) * l.tiles;
+        e.pad_ = 0;
+        e.hist = (double*)(base + l.hist_off);
+        e.counter = (int*)(base + l.ints_off) + 1;
+        e.flag = (int*)(base + l.ints_off);
+    }
+    return MGRIT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mgrit_batched_workspace_bytes(const mgrit_problem* probs, int32_t count, const mgrit_params* p)
+{
+    if (check_batch(probs, count, p) != MGRIT_OK) return 0;
+    BatchPlan bp;
+    if (plan_batch(probs, count, p, nullptr, &bp) != MGRIT_OK) return 0;
+    return bp.total;
+}
+
+int mgrit_cycle_batched(const mgrit_problem* probs, int32_t count, const mgrit_params* p, void* workspace,
+                        size_t ws_bytes, double* res_hist, int32_t* iters, int32_t* status, void* stream)
+{
+    int rc = check_batch(probs, count, p);
+    if (rc) return rc;
+    if (workspace == nullptr || res_hist == nullptr || iters == nullptr || status == nullptr)
+        return fail(MGRIT_EINVAL, "NULL workspace or host output");
+    if (((uintptr_t)workspace & 255) != 0) return fail(MGRIT_EINVAL, "workspace must be 256-byte aligned");
+    for (int i = 0; i < count; ++i)
+        if (probs[i].u0 == nullptr || probs[i].u == nullptr) return fail(MGRIT_EINVAL, "problem %d: NULL array", i);
+    char* ws = (char*)workspace;
+    BatchPlan bp;
+    if ((rc = plan_batch(probs, count, p, ws, &bp))) return rc;
+    if (ws_bytes < bp.total) return fail(MGRIT_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, bp.total);
+    hipStream_t st = (hipStream_t)stream;
+    struct ScratchScope {
+        explicit ScratchScope(char* q) { tl_tile_scratch = q; }
+        ~ScratchScope() { tl_tile_scratch = nullptr; }
+    } scope(bp.any_split ? ws + bp.tile_off : nullptr);
+
+    // tables
+    char* tables = ws + bp.tables_off;
+    HIP_TRY(hipMemcpyAsync(tables, bp.host_args.data(), sizeof(SweepArgs) * bp.host_args.size(),
+                           hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    const size_t args_bytes = sizeof(SweepArgs) * bp.host_args.size();
+    if (!bp.host_ints.empty()) {
+        HIP_TRY(hipMemcpyAsync(tables + align256(args_bytes), bp.host_ints.data(), sizeof(int) * bp.host_ints.size(),
+                               hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    }
+    HIP_TRY(hipMemcpyAsync(ws + bp.norm_off, bp.host_norm.data(), sizeof(mgk::BatchNorm) * (size_t)count,
+                           hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+    int* converged = (int*)(ws + bp.conv_off);
+    if ((rc = launch_aux([&] { return mgk::launch_clear_ints(converged, 1, st); }, st))) return rc;
+    // initial iterates
+    for (int i = 0; i < count; ++i) {
+        const mgrit_problem& q = probs[i];
+        const int64_t nl0 = (p->storage == 0) ? (int64_t)q.nt + 1 : (int64_t)(q.nt / p->m) + 1;
+        int* ints = (int*)(ws + bp.ly_off[i] + bp.ly[i].ints_off);
+        if ((rc = launch_aux([&] { return mgk::launch_broadcast(q.u0, q.u, q.scheme.nx, p->init == 0 ? nl0 : 1, st); },
+                             st)))
+            return rc;
+        if ((rc = launch_aux([&] { return mgk::launch_clear_ints(ints, 4, st); }, st))) return rc;
+    }
+    // HIP's host-to-device copies above come from pageable memory: finish them
+    // before the host vectors go out of scope
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+
+    const int k0 = probs[0].scheme.k, st0 = probs[0].scheme.stepper;
+    auto run_phases = [&](const std::vector<BatchPhase>& phases, size_t base_index) -> int {
+        for (size_t ph = 0; ph < phases.size(); ++ph) {
+            const BatchPhase& P = phases[ph];
+            const SweepArgs* dargs = (const SweepArgs*)(tables + P.args_off);
+            for (const BatchBucket& b : P.buckets) {
+                mgk::BatchLaunch t;
+                t.args = dargs;
+                t.offset = (const int*)(tables + b.dev_off);
+                t.problem = t.offset + b.offset.size();
+                t.nprob = (int)b.probs.size();
+                t.nblocks = b.nblocks;
+                t.end_mode = P.end_mode;
+                t.ragged = b.ragged;
+                PendingEvent pe;
+                if (g_prof) {
+                    pe.kc = P.kc;
+                    pe.phi_lines = 0;
+                    pe.cells = 0;
+                    for (int i : b.probs) {
+                        const double phi = bp.host_phi[(base_index + ph) * count + i];
+                        pe.phi_lines += phi;
+                        pe.cells += phi * (double)probs[i].scheme.nx;
+                    }
+                    HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
+                    HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
+                    HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
+                }
+                hipError_t e = mgk::launch_batch(t, b.cfg, k0, st0, st);
+                if (e != hipSuccess) return hip_fail(e, "batched sweep kernel launch");
+                if (g_prof) {
+                    HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
+                    g_pending.push_back(pe);
+                }
+            }
+            for (int i : P.split) {
+                const SweepArgs& a = bp.host_args[(base_index + ph) * count + i];
+                int r = launch(P.kc, a, &probs[i].scheme, st, bp.host_phi[(base_index + ph) * count + i]);
+                if (r) return r;
+            }
+        }
+        return MGRIT_OK;
+    };
+    int* pinned = pinned_flags();
+    if (!pinned) return fail(MGRIT_EHIP, "hipHostMalloc of the stop-flag buffer failed");
+    const mgk::BatchNorm* dnorm = (const mgk::BatchNorm*)(ws + bp.norm_off);
+    for (int k = 0;; ++k) {
+        if ((rc = run_phases(bp.phA, 0))) return rc;
+        if ((rc = launch_aux([&] { return mgk::launch_reduce_norm_batch(dnorm, count, p->tol, converged, st); }, st)))
+            return rc;
+        if (k == p->max_iter) break;
+        if ((rc = run_phases(bp.phB, bp.phA.size()))) return rc;
+        if ((k + 1) % p->sync_every == 0) {
+            HIP_TRY(hipMemcpyAsync(pinned, converged, sizeof(int), hipMemcpyDeviceToHost, st), "hipMemcpyAsync");
+            HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+            if (pinned[0] >= count) break;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (bp.any_split) {
+        unsigned long long w = 0;
+        HIP_TRY(hipMemcpy(&w, ws + bp.tile_off, sizeof(w), hipMemcpyDeviceToHost), "hipMemcpy");
+        if (w != 0) return fail(MGRIT_EHIP, "tiled sweep: workgroups of a line failed to synchronise");
+    }
+    const int H = p->max_iter + 1;
+    for (int i = 0; i < count; ++i) {
+        int ints[2];
+        HIP_TRY(hipMemcpy(ints, bp.host_norm[i].flag, sizeof(int) * 2, hipMemcpyDeviceToHost), "hipMemcpy");
+        const int nres = ints[1];
+        if (nres < 1 || nres > H) return fail(MGRIT_EHIP, "problem %d: inconsistent residual counter %d", i, nres);
+        for (int j = 0; j < H; ++j) res_hist[(size_t)i * H + j] = 0.0;
+        HIP_TRY(hipMemcpy(res_hist + (size_t)i * H, bp.host_norm[i].hist, sizeof(double) * (size_t)nres,
+                          hipMemcpyDeviceToHost), "hipMemcpy");
+        iters[i] = nres - 1;
+        status[i] = ints[0] ? MGRIT_OK : MGRIT_NOT_CONVERGED;
+    }
+    return MGRIT_OK;
 }
 
 }  // extern "C"

@@ -123,6 +123,56 @@ __global__ void reduce_norm_kernel(const double* partial, int n, double* hist, i
     }
 }
 
+// the same for a batch of problems, one workgroup per problem; a problem that
+// converges here also counts itself in *converged
+__global__ void reduce_norm_batch_kernel(const BatchNorm* tab, double tol, int* converged)
+{
+    const BatchNorm e = tab[blockIdx.x];
+    if (*e.flag != 0) return;
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < e.n; i += blockDim.x) s += e.partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double nrm = sqrt(red[0]);
+        const int k = *e.counter;
+        e.hist[k] = nrm;
+        *e.counter = k + 1;
+        if (tol >= 0.0 && nrm < tol) {
+            *e.flag = 1;
+            atomicAdd(converged, 1);
+        }
+    }
+}
+
+hipError_t launch_reduce_norm_batch(const BatchNorm* tab, int count, double tol, int* converged, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_norm_batch_kernel, dim3(count), dim3(256), 0, s, tab, tol, converged);
+    return hipGetLastError();
+}
+
+template <int K, int ST>
+hipError_t launch_batch_ks(const BatchLaunch& t, const KernelCfg& cfg, hipStream_t s);
+
+hipError_t launch_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
+{
+    if (t.nblocks <= 0) return hipSuccess;
+    if (k == 0) {
+        if (stepper == 1) return launch_batch_ks<0, 1>(t, cfg, s);
+        if (stepper == 2) return launch_batch_ks<0, 2>(t, cfg, s);
+        return launch_batch_ks<0, 3>(t, cfg, s);
+    }
+    if (stepper == 1) return launch_batch_ks<2, 1>(t, cfg, s);
+    if (stepper == 2) return launch_batch_ks<2, 2>(t, cfg, s);
+    return launch_batch_ks<2, 3>(t, cfg, s);
+}
+
 hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s)
 {
     if (nlines <= 0) return hipSuccess;

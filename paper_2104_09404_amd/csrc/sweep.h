@@ -65,6 +65,29 @@ struct SweepArgs {
     double* tile_pub;       // published edge data: groups x tiles x 2 x kTileSlot
 };
 
+// One batched launch: workgroup b runs chunk b - offset[i] of problem
+// problem[i], i the last bucket entry with offset[i] <= b, with the arguments
+// args[problem[i]] (device memory).
+struct BatchLaunch {
+    const SweepArgs* args;
+    const int* offset;   // nprob entries, ascending, offset[0] = 0
+    const int* problem;  // nprob entries
+    int nprob;
+    int nblocks;
+    int end_mode;        // END_NONE, END_CSTEP or END_RESTRICT (every entry of args has it)
+    int ragged;          // some problem's line is not a multiple of the cells per thread
+};
+
+// per-problem residual reduction of a batch
+struct BatchNorm {
+    const double* partial;  // n per-chunk partial sums
+    int n;
+    int pad_;
+    double* hist;
+    int* counter;
+    int* flag;
+};
+
 // tiled lines: doubles per published slot, words between arrival counters
 // (one 128-byte line each, so that groups do not contend for a line), and the
 // largest resident grid the synchronisation scratch is sized for
@@ -129,6 +152,21 @@ struct KernelCfg {
     X(1, 16)            \
     X(2, 16)
 
+// (cells per thread, waves) pairs compiled for batches of problems (the ones
+// the configuration choice makes for throughput and latency launches)
+#define MGK_BATCH_CFG_LIST(X) \
+    X(1, 1)                   \
+    X(2, 1)                   \
+    X(4, 1)                   \
+    X(1, 2)                   \
+    X(2, 2)                   \
+    X(4, 2)                   \
+    X(2, 4)                   \
+    X(4, 4)                   \
+    X(2, 8)                   \
+    X(4, 8)                   \
+    X(8, 8)
+
 // (cells per thread, waves) pairs compiled for the adjoint; the line must be a
 // multiple of the cells per thread
 #define MGK_ADJ_CFG_LIST(X) \
@@ -169,6 +207,8 @@ inline size_t smem_bytes(int cpt, int nw)
 
 hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
 hipError_t launch_tiled(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
+hipError_t launch_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
+hipError_t launch_reduce_norm_batch(const BatchNorm* tab, int count, double tol, int* converged, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int stepper, int store_mode, hipStream_t s);
 hipError_t launch_tiled_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int stepper, int store_mode,
                                 hipStream_t s);

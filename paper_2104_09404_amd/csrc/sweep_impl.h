@@ -318,7 +318,7 @@ __device__ __forceinline__ double line_sqdiff(const double (&a)[CPT], const doub
 // One chunk (one line) per workgroup.  See SweepArgs for the roles; END is
 // the compile-time end mode.
 template <int CPT, int NW, int K, int ST, bool RAG, int END>
-__device__ __forceinline__ void sweep_body(const SweepArgs& a)
+__device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
 {
     if (a.flag != nullptr && *a.flag != 0) return;
     extern __shared__ double smem_raw[];
@@ -328,7 +328,6 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a)
     g.init(a.nx);
     int par = 0;
     const int64_t nx = a.nx;
-    const int c = blockIdx.x;
 
     const double* src = (a.side_in != nullptr && c > 0) ? a.side_in + (int64_t)c * nx
                                                         : a.ustart + (int64_t)c * a.ustart_stride * nx;
@@ -402,25 +401,100 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a)
 template <int CPT, int NW, int K, int ST, bool RAG>
 __global__ __launch_bounds__(64 * NW) void relax_f_kernel(SweepArgs a)
 {
-    sweep_body<CPT, NW, K, ST, RAG, END_NONE>(a);
+    sweep_body<CPT, NW, K, ST, RAG, END_NONE>(a, blockIdx.x);
 }
 
 template <int CPT, int NW, int K, int ST, bool RAG>
 __global__ __launch_bounds__(64 * NW) void relax_fc_kernel(SweepArgs a)
 {
-    sweep_body<CPT, NW, K, ST, RAG, END_CSTEP>(a);
+    sweep_body<CPT, NW, K, ST, RAG, END_CSTEP>(a, blockIdx.x);
 }
 
 template <int CPT, int NW, int K, int ST, bool RAG>
 __global__ __launch_bounds__(64 * NW) void relax_fr_kernel(SweepArgs a)
 {
-    sweep_body<CPT, NW, K, ST, RAG, END_RESTRICT>(a);
+    sweep_body<CPT, NW, K, ST, RAG, END_RESTRICT>(a, blockIdx.x);
 }
 
 template <int CPT, int NW, int K, int ST, bool RAG>
 __global__ __launch_bounds__(64 * NW) void phi_kernel(SweepArgs a)
 {
-    sweep_body<CPT, NW, K, ST, RAG, END_PHI>(a);
+    sweep_body<CPT, NW, K, ST, RAG, END_PHI>(a, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// batches of independent problems: one launch covers the chunks of every
+// problem of a bucket (problems sharing a configuration); workgroup b finds
+// its problem by binary search over the bucket's chunk offsets and takes that
+// problem's arguments from a device table
+// ---------------------------------------------------------------------------
+template <int CPT, int NW, int K, int ST, bool RAG, int END>
+__device__ __forceinline__ void batch_body(const BatchLaunch& t)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = t.nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t.offset[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const SweepArgs a = t.args[t.problem[lo]];
+    sweep_body<CPT, NW, K, ST, RAG, END>(a, b - t.offset[lo]);
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG>
+__global__ __launch_bounds__(64 * NW) void batch_f_kernel(BatchLaunch t)
+{
+    batch_body<CPT, NW, K, ST, RAG, END_NONE>(t);
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG>
+__global__ __launch_bounds__(64 * NW) void batch_fc_kernel(BatchLaunch t)
+{
+    batch_body<CPT, NW, K, ST, RAG, END_CSTEP>(t);
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG>
+__global__ __launch_bounds__(64 * NW) void batch_fr_kernel(BatchLaunch t)
+{
+    batch_body<CPT, NW, K, ST, RAG, END_RESTRICT>(t);
+}
+
+template <class Fn>
+static hipError_t launch_batch_fn(Fn fn, const BatchLaunch& t, int nw, size_t shmem, hipStream_t s)
+{
+    if (shmem > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3(t.nblocks), dim3(64 * nw), shmem, s, t);
+    return hipGetLastError();
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG>
+static hipError_t launch_batch_role(const BatchLaunch& t, hipStream_t s)
+{
+    const size_t shmem = smem_bytes(CPT, NW);
+    switch (t.end_mode) {
+    case END_NONE: return launch_batch_fn(batch_f_kernel<CPT, NW, K, ST, RAG>, t, NW, shmem, s);
+    case END_CSTEP: return launch_batch_fn(batch_fc_kernel<CPT, NW, K, ST, RAG>, t, NW, shmem, s);
+    case END_RESTRICT: return launch_batch_fn(batch_fr_kernel<CPT, NW, K, ST, RAG>, t, NW, shmem, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int K, int ST>
+hipError_t launch_batch_ks(const BatchLaunch& t, const KernelCfg& cfg, hipStream_t s)
+{
+    if (t.nblocks <= 0) return hipSuccess;
+#define MGK_CASE(C, W)                                                                  \
+    if (cfg.cpt == C && cfg.nw == W) {                                                  \
+        if (C > 1 && t.ragged) return launch_batch_role<C, W, K, ST, C == 1 ? false : true>(t, s); \
+        return launch_batch_role<C, W, K, ST, false>(t, s);                             \
+    }
+    MGK_BATCH_CFG_LIST(MGK_CASE)
+#undef MGK_CASE
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

@@ -26,7 +26,8 @@ KERNEL_CLASSES = ["phi", "relax_fc_l0", "relax_fr_l0", "relax_fc_coarse", "relax
 EXPORTED = ["mgrit_phi", "mgrit_serial", "mgrit_relax", "mgrit_residual", "mgrit_workspace_bytes",
             "mgrit_cycle", "mgrit_last_error", "mgrit_set_profiling", "mgrit_get_profile",
             "mgrit_kernel_config", "mgrit_set_kernel_config", "mgrit_phi_vjp", "mgrit_checkpoints",
-            "mgrit_adjoint_workspace_bytes", "mgrit_adjoint", "mgrit_tiled_config", "mgrit_set_tiled_config"]
+            "mgrit_adjoint_workspace_bytes", "mgrit_adjoint", "mgrit_tiled_config", "mgrit_set_tiled_config",
+            "mgrit_batched_workspace_bytes", "mgrit_cycle_batched"]
 
 
 class MgritError(RuntimeError):
@@ -66,6 +67,19 @@ class Params(C.Structure):
         ("sync_every", C.c_int32),
         ("dt", C.c_double),
         ("tol", C.c_double),
+    ]
+
+
+class Problem(C.Structure):
+    """Mirror of ``mgrit_problem`` (one problem of a batch)."""
+
+    _fields_ = [
+        ("scheme", Scheme),
+        ("nt", C.c_int32),
+        ("pad_", C.c_int32),
+        ("dt", C.c_double),
+        ("u0", C.c_void_p),
+        ("u", C.c_void_p),
     ]
 
 
@@ -109,9 +123,14 @@ def load(path: str = LIB_PATH):
     L.mgrit_adjoint_workspace_bytes.argtypes = [S, i32, i32, i32]
     L.mgrit_adjoint_workspace_bytes.restype = C.c_size_t
     L.mgrit_adjoint.argtypes = [S, C.c_double, i32, i32, i32, dp, dp, dp, vp, C.c_size_t, vp]
+    PR = C.POINTER(Problem)
+    L.mgrit_batched_workspace_bytes.argtypes = [PR, i32, P]
+    L.mgrit_batched_workspace_bytes.restype = C.c_size_t
+    L.mgrit_cycle_batched.argtypes = [PR, i32, P, vp, C.c_size_t, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), vp]
     for name in EXPORTED:
         if name in ("mgrit_last_error", "mgrit_set_profiling", "mgrit_workspace_bytes",
-                    "mgrit_adjoint_workspace_bytes"):
+                    "mgrit_adjoint_workspace_bytes", "mgrit_batched_workspace_bytes"):
             continue
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -232,6 +251,48 @@ def set_kernel_config(nx_lo: int, nx_hi: int, cpt: int, waves: int, latency: boo
 
 def clear_kernel_config():
     _check(load().mgrit_set_kernel_config(0, 0, 0, 0, 0))
+
+
+def problem_table(problems):
+    """ctypes array of mgrit_problem from (scheme, nt, dt, u0, u) tuples
+    (u0, u: float64 GPU tensors)."""
+    arr = (Problem * len(problems))()
+    for i, (sch, nt, dt, u0, u) in enumerate(problems):
+        arr[i].scheme = sch
+        arr[i].nt = nt
+        arr[i].dt = dt
+        arr[i].u0 = _ptr(u0)
+        arr[i].u = _ptr(u)
+    return arr
+
+
+def batched_workspace_bytes(problems, p: Params) -> int:
+    arr = problems if isinstance(problems, C.Array) else problem_table(problems)
+    n = load().mgrit_batched_workspace_bytes(arr, len(arr), C.byref(p))
+    if n == 0:
+        raise MgritError(MGRIT_EINVAL, load().mgrit_last_error().decode())
+    return n
+
+
+def cycle_batched(problems, p: Params, workspace=None, stream=None):
+    """FAS-MGRIT on a batch of problems; returns (histories, iters, status),
+    histories[i] the residual norms r_0..r_{iters[i]} of problem i."""
+    import torch
+
+    arr = problems if isinstance(problems, C.Array) else problem_table(problems)
+    count = len(arr)
+    if workspace is None:
+        nbytes = batched_workspace_bytes(arr, p)
+        workspace = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
+    H = p.max_iter + 1
+    hist = (C.c_double * (count * H))()
+    iters = (C.c_int32 * count)()
+    status = (C.c_int32 * count)()
+    _check(load().mgrit_cycle_batched(arr, count, C.byref(p), C.c_void_p(workspace.data_ptr()),
+                                      workspace.numel() * workspace.element_size(), hist, iters, status,
+                                      _stream(stream)))
+    hs = [list(hist[i * H:i * H + iters[i] + 1]) for i in range(count)]
+    return hs, list(iters), list(status)
 
 
 def tiled_config(nx: int):

@@ -124,3 +124,30 @@ def test_split_line_choice(lib):
     s2 = mgrit.scheme(4096)
     n_one = lib.mgrit_workspace_bytes(C.byref(s2), C.byref(p))
     assert n_split > 2 * n_one
+
+
+def test_batch_validation_without_gpu(lib):
+    """Batches: the workspace is sized on the host; mixed k or stepper, fewer
+    than two levels or an empty batch are rejected before any device call."""
+    from paper_2104_09404_amd import mgrit
+
+    p = mgrit.params(0, 0.0, 8, 2, relax=1, max_iter=2, tol=-1.0, storage=1)
+    probs = [(mgrit.scheme(256), 1024, 1e-3, None, None), (mgrit.scheme(6002, flux=1, a=0.7), 24008, 1e-4, None, None)]
+    n = mgrit.batched_workspace_bytes(probs, p)
+    # at least the per-problem coarse level, side buffer, plus the split-line scratch
+    assert n > 8 * (2 * 129 * 256 + 2 * 3002 * 6002) + 2 * 1024 * 1024
+    arr = mgrit.problem_table(probs)
+    assert lib.mgrit_batched_workspace_bytes(arr, 0, C.byref(p)) == 0
+    bad = [(mgrit.scheme(256), 1024, 1e-3, None, None), (mgrit.scheme(256, stepper=1), 1024, 1e-3, None, None)]
+    assert lib.mgrit_batched_workspace_bytes(mgrit.problem_table(bad), 2, C.byref(p)) == 0
+    assert b"same k and stepper" in lib.mgrit_last_error()
+    p1 = mgrit.params(0, 0.0, 8, 1)
+    assert lib.mgrit_batched_workspace_bytes(arr, 2, C.byref(p1)) == 0
+    bad_nt = [(mgrit.scheme(256), 1001, 1e-3, None, None)]
+    assert lib.mgrit_batched_workspace_bytes(mgrit.problem_table(bad_nt), 1, C.byref(p)) == 0
+    assert b"problem 0" in lib.mgrit_last_error()
+    hist = (C.c_double * 8)()
+    its = (C.c_int32 * 2)()
+    st = (C.c_int32 * 2)()
+    rc = lib.mgrit_cycle_batched(arr, 2, C.byref(p), None, 0, hist, its, st, None)
+    assert rc == mgrit.MGRIT_EINVAL
