@@ -1170,6 +1170,9 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
 // ---------------------------------------------------------------------------
 namespace {
 
+// longest line whose serial solve a batch runs on one workgroup
+const int kMaxBatchSerialLine = 64 * 16 * 8;
+
 struct BatchBucket {
     KernelCfg cfg;
     int ragged;
@@ -1307,14 +1310,22 @@ int plan_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p,
                 P.cells += r.phi_lines * (double)probs[i].scheme.nx;
                 KernelCfg c;
                 int t = 0;
+                const bool serial = r.a.nchunks == 1 && r.a.end_mode == mgk::END_NONE;
                 if (choose_tiled(probs[i].scheme.nx, &c, &t)) {
-                    P.split.push_back(i);
-                    continue;
+                    if (serial && probs[i].scheme.nx <= kMaxBatchSerialLine) {
+                        // one workgroup of 16 waves x 8 cells: every problem's serial
+                        // solve runs at once instead of one split launch after another
+                        c = KernelCfg{8, 16};
+                    } else {
+                        P.split.push_back(i);
+                        continue;
+                    }
+                } else {
+                    // serial solves (one chunk per problem) take the latency configuration
+                    const int nl = serial ? 1 : (int)std::min<long long>(total_lines, 1 << 30);
+                    if (!choose_cfg(probs[i].scheme.nx, nl, &c))
+                        return fail(MGRIT_EUNSUPPORTED, "problem %d: no kernel configuration", i);
                 }
-                // serial solves (one chunk per problem) take the latency configuration
-                const int nl = (r.a.nchunks == 1) ? 1 : (int)std::min<long long>(total_lines, 1 << 30);
-                if (!choose_cfg(probs[i].scheme.nx, nl, &c))
-                    return fail(MGRIT_EUNSUPPORTED, "problem %d: no kernel configuration", i);
                 const int rag = (c.cpt > 1 && probs[i].scheme.nx % c.cpt != 0) ? 1 : 0;
                 BatchBucket* bk = nullptr;
                 for (BatchBucket& b : P.buckets)

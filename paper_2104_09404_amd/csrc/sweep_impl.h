@@ -487,6 +487,14 @@ template <int K, int ST>
 hipError_t launch_batch_ks(const BatchLaunch& t, const KernelCfg& cfg, hipStream_t s)
 {
     if (t.nblocks <= 0) return hipSuccess;
+    if (cfg.cpt == 8 && cfg.nw == 16) {
+        // serial solves of lines up to 8192 cells (F-steps only: the other
+        // roles spill registers at this size)
+        if (t.end_mode != END_NONE) return hipErrorInvalidValue;
+        const size_t shmem = smem_bytes(8, 16);
+        if (t.ragged) return launch_batch_fn(batch_f_kernel<8, 16, K, ST, true>, t, 16, shmem, s);
+        return launch_batch_fn(batch_f_kernel<8, 16, K, ST, false>, t, 16, shmem, s);
+    }
 #define MGK_CASE(C, W)                                                                  \
     if (cfg.cpt == C && cfg.nw == W) {                                                  \
         if (C > 1 && t.ragged) return launch_batch_role<C, W, K, ST, C == 1 ? false : true>(t, s); \
