@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the reference-oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward ratio (its split-line launches are cooperative)")
     return ap.parse_args()
 
 
@@ -239,7 +241,7 @@ def main():
         "level0_relax_cell_steps_per_s": (prof["relax_fc_l0"]["cell_steps"] + prof["relax_fr_l0"]["cell_steps"])
         / ((prof["relax_fc_l0"]["ms"] + prof["relax_fr_l0"]["ms"]) * 1e-3),
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
-        "adjoint_forward_ratio": adjoint_ratio(mgrit),
+        "adjoint_forward_ratio": None if args.no_adjoint else adjoint_ratio(mgrit),
         "mgrit_converges": bool(np.isfinite(hist[-1]) and hist[-1] < 1e-10),
         "gpu_serial_ms": gpu_serial_ms(mgrit, s, pb, u0),
     }

@@ -58,7 +58,7 @@ __device__ __forceinline__ void op_AT(const double (&v)[CPT], const double (&mu)
 {
     // phase 1
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) sa.lineV[g.j0 + q] = v[q];
+    for (int q = 0; q < CPT; ++q) sa.lineV[g.own(q)] = v[q];
     sa.MF[g.t] = mu[0];
     sa.ML[g.t] = mu[CPT - 1];
     __syncthreads();

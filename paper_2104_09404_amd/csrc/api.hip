@@ -84,9 +84,10 @@ bool choose_cfg(int nx, int nlines, KernelCfg* out)
         }
     if (nx > kMaxLine) return false;
     if (latency) {
-        // per-step latency of a single line, measured on MI355X: two cells per
-        // thread over up to 8 waves beats one cell per thread over 16 waves
-        static const KernelCfg pref[] = {{1, 1}, {1, 2}, {2, 2}, {2, 4}, {2, 8}, {4, 8}, {8, 8}};
+        // per-step latency of a single line, measured on MI355X (1024 cells:
+        // 1.08 us per stage with 4 cells x 4 waves, 1.13 with 2 x 8, 1.58 with
+        // 1 x 16): few cells per thread do not pay for the extra waves
+        static const KernelCfg pref[] = {{1, 1}, {1, 2}, {2, 2}, {2, 4}, {4, 4}, {4, 8}, {8, 8}};
         for (const KernelCfg& c : pref)
             if (c.cpt * c.nw * 64 >= nx) {
                 *out = c;

@@ -197,7 +197,7 @@ struct KernelCfg {
 
 inline size_t tiled_smem_bytes(int cpt, int nw)
 {
-    return sizeof(double) * (64 * (size_t)nw * (size_t)cpt + 6 + 2 * 64 * (size_t)nw + (size_t)nw + 40);
+    return sizeof(double) * (64 * (size_t)nw * (size_t)cpt + 7 + 2 * 64 * (size_t)nw + (size_t)nw + 40);
 }
 
 inline size_t smem_bytes(int cpt, int nw)

@@ -41,6 +41,16 @@ __device__ __forceinline__ int wrapi(int i, int n)
 // Max over the 64 lanes of a wave, returned uniformly (NaN-ignoring like fmax).
 // DPP moves within quads, half-rows and rows, then the row broadcasts of lanes
 // 15 and 31 leave the maximum in lane 63, which is read back as a scalar.
+// Full-mask moves take no "old" operand; the two row broadcasts keep the old
+// value in the rows they do not write.
+template <int CTRL>
+__device__ __forceinline__ double dpp_all(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_move(double v)
 {
@@ -53,10 +63,10 @@ __device__ __forceinline__ double dpp_move(double v)
 
 __device__ __forceinline__ double wave_max(double v)
 {
-    v = fmax(v, dpp_move<0xb1, 0xf>(v));   // quad_perm [1,0,3,2]
-    v = fmax(v, dpp_move<0x4e, 0xf>(v));   // quad_perm [2,3,0,1]
-    v = fmax(v, dpp_move<0x141, 0xf>(v));  // row_half_mirror
-    v = fmax(v, dpp_move<0x140, 0xf>(v));  // row_mirror
+    v = fmax(v, dpp_all<0xb1>(v));         // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_all<0x4e>(v));         // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_all<0x141>(v));        // row_half_mirror
+    v = fmax(v, dpp_all<0x140>(v));        // row_mirror
     v = fmax(v, dpp_move<0x142, 0xa>(v));  // row_bcast:15 into rows 1 and 3
     v = fmax(v, dpp_move<0x143, 0xc>(v));  // row_bcast:31 into rows 2 and 3
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
@@ -85,7 +95,14 @@ struct Geo {
     int right;    // thread owning the cell after the last owned one (periodic)
     bool active;  // owns at least one cell
     bool ragged;  // owns fewer than CPT cells
-    int halo[6];  // line indices of window positions 0,1,2 and CPT+3..CPT+5
+    int halo[6];  // LDS slots of window positions 0,1,2 and CPT+3..CPT+5
+
+    // LDS slot of cell c: the line is stored transposed, cell c at
+    // (c mod CPT) * threads + c / CPT, so that the q-th cells of consecutive
+    // threads (and every window position) are consecutive doubles: no bank
+    // conflicts for any cells per thread
+    static __device__ __forceinline__ int slot(int c) { return (c % CPT) * (64 * NW) + c / CPT; }
+    __device__ __forceinline__ int own(int q) const { return q * (64 * NW) + t; }
 
     __device__ __forceinline__ void init(int nx_)
     {
@@ -100,14 +117,14 @@ struct Geo {
         right = active ? ((t == nact - 1) ? 0 : t + 1) : t;
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            halo[p] = wrapi(j0 - 3 + p, nx);
-            halo[3 + p] = wrapi(j0 + CPT + p, nx);
+            halo[p] = slot(wrapi(j0 - 3 + p, nx));
+            halo[3 + p] = slot(wrapi(j0 + CPT + p, nx));
         }
     }
 };
 
 // Shared-memory layout: line[64*NW*CPT] | bm[64*NW] | bp[64*NW] | wred[NW] | amax[2*NW].
-// The line array covers every thread's cells, so stage values are written
+// The line array (transposed, see Geo::slot) covers every thread's cells, so stage values are written
 // without predicates; slots nx.. are scratch.  amax holds the per-wave maxima
 // of the alpha_LF reduction, double-buffered by stage parity.
 template <int CPT, int NW>
@@ -137,7 +154,7 @@ __device__ __forceinline__ void op_A(const double (&V)[CPT], double (&A)[CPT], c
                                      const Smem<CPT, NW>& sm, const PhiConst& pc, int& par)
 {
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) sm.line[g.j0 + q] = V[q];
+    for (int q = 0; q < CPT; ++q) sm.line[g.own(q)] = V[q];
     __syncthreads();
 
     // window w[p] = cell j0 - 3 + p, p = 0..CPT+5
@@ -148,7 +165,7 @@ __device__ __forceinline__ void op_A(const double (&V)[CPT], double (&A)[CPT], c
         // positions past the end of the line wrap around to its first cells
 #pragma unroll
         for (int q = 0; q < CPT; ++q)
-            if (q >= g.nvalid) w[3 + q] = sm.line[wrapi(g.j0 + q, g.nx)];
+            if (q >= g.nvalid) w[3 + q] = sm.line[g.slot(wrapi(g.j0 + q, g.nx))];
     }
     double um[CPT], up[CPT];
     if (K == 0) {

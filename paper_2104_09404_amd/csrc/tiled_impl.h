@@ -35,8 +35,11 @@ namespace mgk {
 
 constexpr long long kTileSpinLimit = 1LL << 22;
 
-// LDS: tl[T + 6] | bm[64 NW] | bp[64 NW] | amax[NW] | misc[40]
-//   tl: ghost cells -3..-1 at 0..2, own cells at 3..Tv+2, ghosts Tv..Tv+2 at Tv+3..Tv+5
+// LDS: tl[T + 7] | bm[64 NW] | bp[64 NW] | amax[NW] | misc[40]
+//   tl: the tile's cells transposed (cell c at (c mod CPT) * threads + c / CPT,
+//   so that every window position is read lane-contiguously, free of bank
+//   conflicts), ghost cells -3..-1 at T..T+2 and Tv..Tv+2 at T+3..T+5, one
+//   scratch slot at T+6 for window positions past the ghosts
 //   misc[0] alpha_LF, [1..2] (Fa, Fb) of the tile's left edge interface,
 //   [3..4] of its right edge interface, [5..10] the left neighbour's
 //   right-edge data, [11..16] the right neighbour's left-edge data,
@@ -51,7 +54,7 @@ struct TSmem {
     __device__ __forceinline__ void init(double* base)
     {
         tl = base;
-        bm = tl + 64 * NW * CPT + 6;
+        bm = tl + 64 * NW * CPT + 7;
         bp = bm + 64 * NW;
         amax = bp + 64 * NW;
         misc = amax + NW;
@@ -74,6 +77,18 @@ struct TGeo {
     int gk;         // ghost handled by this thread: 0..2 left, 3..5 right, -1 none
     int gpos;       // LDS position of that ghost
     int64_t gcell;  // its cell in the line (periodic)
+    int halo[6];    // LDS slots of window positions 0..2 and CPT+3..CPT+5
+
+    // LDS slot of tile cell c, -3 <= c (see TSmem)
+    __device__ __forceinline__ int tslot(int c) const
+    {
+        const int T = 64 * NW * CPT;
+        if (c < 0) return T + 3 + c;
+        if (c < Tv) return (c % CPT) * (64 * NW) + c / CPT;
+        if (c < Tv + 3) return T + 3 + (c - Tv);
+        return T + 6;
+    }
+    __device__ __forceinline__ int own(int q) const { return q * (64 * NW) + t; }
 
     __device__ __forceinline__ void init(int64_t nx, int tile, int G)
     {
@@ -87,13 +102,17 @@ struct TGeo {
         gk = (t < 6) ? t : -1;
         gpos = 0;
         gcell = 0;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            halo[p] = active ? tslot(j0 - 3 + p) : 64 * NW * CPT + 6;
+            halo[3 + p] = active ? tslot(j0 + CPT + p) : 64 * NW * CPT + 6;
+        }
         if (gk >= 0) {
             int64_t cell;
+            gpos = 64 * NW * CPT + gk;
             if (gk < 3) {
-                gpos = gk;
                 cell = x0 - 3 + gk;
             } else {
-                gpos = Tv + gk;  // Tv + 3 + (gk - 3)
                 cell = x0 + Tv + (gk - 3);
             }
             cell %= nx;
@@ -138,20 +157,20 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
     if (g.active) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q)
-            if (!RAG || q < g.nvalid) sm.tl[3 + g.j0 + q] = V[q];
+            if (!RAG || q < g.nvalid) sm.tl[g.own(q)] = V[q];
     }
     if (g.gk >= 0) sm.tl[g.gpos] = gv;
     __syncthreads();
 
     // window w[p] = tile cell j0 - 3 + p, p = 0..CPT+5; past the ragged end it
-    // continues into the right ghost cells
+    // continues into the right ghost cells (then the scratch slot)
     double w[CPT + 6];
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) w[3 + q] = (RAG && q >= g.nvalid) ? sm.tl[3 + g.j0 + q] : V[q];
+    for (int q = 0; q < CPT; ++q) w[3 + q] = (RAG && q >= g.nvalid) ? sm.tl[g.tslot(g.j0 + q)] : V[q];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-        w[p] = sm.tl[g.j0 + p];
-        w[CPT + 3 + p] = sm.tl[g.j0 + CPT + 3 + p];
+        w[p] = sm.tl[g.halo[p]];
+        w[CPT + 3 + p] = sm.tl[g.halo[3 + p]];
     }
     double um[CPT], up[CPT];
     double um_l = 0.0, up_r = 0.0;  // u^- in ghost cell -1, u^+ in ghost cell Tv

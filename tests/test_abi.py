@@ -85,10 +85,12 @@ def test_kernel_config_choice(lib):
         for nlines in (1, 64, 512):
             cpt, w = mgrit.kernel_config(nx, nlines)
             assert cpt * w * 64 >= nx
-    # few lines: more threads per line than for many lines
-    c1, w1 = mgrit.kernel_config(1024, 1)
-    c2, w2 = mgrit.kernel_config(1024, 512)
+    # few lines: more threads per line than for many lines (measured on
+    # MI355X; from 1024 cells on, 4 cells x 4 waves wins in both regimes)
+    c1, w1 = mgrit.kernel_config(512, 1)
+    c2, w2 = mgrit.kernel_config(512, 512)
     assert w1 > w2 and c1 < c2
+    assert mgrit.kernel_config(1024, 1) == mgrit.kernel_config(1024, 512) == (4, 4)
     with pytest.raises(mgrit.MgritError):
         mgrit.kernel_config(1 << 20)
     with pytest.raises(mgrit.MgritError):
