@@ -66,6 +66,9 @@ typedef struct {
     double  eps;         /* WENO epsilon (sec 2.1.1: usually 1e-6)                              */
     double  L;           /* domain length                                                        */
     double  alpha_fixed; /* > 0: use this value as alpha_LF instead of the global maximum       */
+    int32_t lf_dx_dt;    /* 1: alpha_LF = dx/dt of the step taken (eq fineLF, and eq coarseLF     */
+                         /*    when rediscretised); overrides alpha_fixed                         */
+    int32_t pad_;
 } orc_scheme;
 
 typedef struct {
@@ -78,7 +81,9 @@ typedef struct {
     int32_t init;        /* 0: initial iterate u^n = u0 for all n; 1: use the u passed in       */
     int32_t coarse_guess;/* 0: eq restriction::u ; 1: plain injection u_{l+1}^i = u_l^{mi}      */
     int32_t exact_coarse;/* 1: Phi_{l+1} := Phi_l applied m times (ideal coarse integrator)     */
-    int32_t pad_;
+    int32_t coarse_integrator; /* levels l >= 1: 0 rediscretisation; 1 zeroth-order (eq           */
+                               /* coarseLFord0), 2 first-order (eq coarseLFord1) fine-integrator   */
+                               /* matching over M = m^l fine steps (eq fineLFxM)                   */
     double  dt;          /* fine time step                                                       */
     double  tol;         /* stop when ||r|| < tol; tol < 0 runs exactly max_iter cycles          */
 } orc_params;
@@ -230,8 +235,11 @@ double orc_spatial_operator(const orc_scheme* s, const double* u, double* A)
 /* ------------------------------------------------------------------------ */
 
 /* out = Phi(u) for one step of size dt.  out may alias u. */
-void orc_phi(const orc_scheme* s, double dt, const double* u, double* out)
+void orc_phi(const orc_scheme* s_in, double dt, const double* u, double* out)
 {
+    orc_scheme sc = *s_in;
+    if (sc.lf_dx_dt) sc.alpha_fixed = (sc.L / (double)sc.nx) / dt;
+    const orc_scheme* s = &sc;
     int n = s->nx;
     size_t bytes = sizeof(double) * (size_t)n;
     double* u0 = (double*)malloc(bytes);
@@ -282,6 +290,72 @@ void orc_serial(const orc_scheme* s, double dt, int32_t nt, const double* u0, do
 }
 
 /* ------------------------------------------------------------------------ */
+/* Fine-integrator matching coarse integrators (sec 3.3.1)                    */
+/* ------------------------------------------------------------------------ */
+
+/* average operator E(v)_i = (v_{i+1} + v_{i-1})/2 and central difference
+   D(v)_i = (v_{i+1} - v_{i-1})/(2 dx) of eq fineLF, periodic */
+static void op_E(int n, const double* v, double* out)
+{
+    for (int i = 0; i < n; ++i) out[i] = (v[wrap(i + 1, n)] + v[wrap(i - 1, n)]) / 2.0;
+}
+
+static void op_D(int n, double dx, const double* v, double* out)
+{
+    for (int i = 0; i < n; ++i) out[i] = (v[wrap(i + 1, n)] - v[wrap(i - 1, n)]) / (2.0 * dx);
+}
+
+/* out = E^j(v) (out may alias v) */
+static void op_Ej(int n, int j, const double* v, double* out)
+{
+    double* a = (double*)malloc(sizeof(double) * (size_t)n);
+    memcpy(out, v, sizeof(double) * (size_t)n);
+    for (int r = 0; r < j; ++r) {
+        op_E(n, out, a);
+        memcpy(out, a, sizeof(double) * (size_t)n);
+    }
+    free(a);
+}
+
+/* Coarse integrator matching M fine steps of eq fineLF (fine step dt):
+     order 0 (eq coarseLFord0, extended to M): out = E^M u - M dt D f(u)
+     order 1 (eq coarseLFord1 from eq fineLFxM): out = E^M u - dt sum_{i=1}^{M} E^{i-1} D f(E^{M-i} u)
+   The sum is evaluated term by term as written. */
+void orc_psi(const orc_scheme* s, int32_t order, int32_t M, double dt, const double* u, double* out)
+{
+    int n = s->nx;
+    double dx = s->L / (double)n;
+    size_t bytes = sizeof(double) * (size_t)n;
+    double* EMu = (double*)malloc(bytes);
+    double* w = (double*)malloc(bytes);
+    double* fw = (double*)calloc((size_t)n, sizeof(double));
+    double* Dfw = (double*)malloc(bytes);
+    double* term = (double*)malloc(bytes);
+    double* sum = (double*)calloc((size_t)n, sizeof(double));
+    op_Ej(n, M, u, EMu);
+    if (order == 0) {
+        for (int i = 0; i < n; ++i) fw[i] = flux_f(s, u[i]);
+        op_D(n, dx, fw, Dfw);
+        for (int i = 0; i < n; ++i) out[i] = EMu[i] - (double)M * dt * Dfw[i];
+    } else {
+        for (int k = 1; k <= M; ++k) {
+            op_Ej(n, M - k, u, w);                 /* E^{M-i} u */
+            for (int i = 0; i < n; ++i) fw[i] = flux_f(s, w[i]);
+            op_D(n, dx, fw, Dfw);                  /* D f(E^{M-i} u) */
+            op_Ej(n, k - 1, Dfw, term);            /* E^{i-1} D f(E^{M-i} u) */
+            for (int i = 0; i < n; ++i) sum[i] += term[i];
+        }
+        for (int i = 0; i < n; ++i) out[i] = EMu[i] - dt * sum[i];
+    }
+    free(EMu);
+    free(w);
+    free(fw);
+    free(Dfw);
+    free(term);
+    free(sum);
+}
+
+/* ------------------------------------------------------------------------ */
 /* MGRIT (sec 3)                                                              */
 /* ------------------------------------------------------------------------ */
 
@@ -300,12 +374,17 @@ typedef struct {
 static double* node(double* base, int n, int nx) { return base + (size_t)n * (size_t)nx; }
 
 /* Phi_(l): the level-l integrator (coarse integrators by rediscretisation, dt_l = m^l dt,
-   sec 3.3; or, with exact_coarse, Phi_(l) = Phi_(0)^{m^l}) */
+   sec 3.3; with exact_coarse, Phi_(l) = Phi_(0)^{m^l}; with a coarse integrator of
+   sec 3.3.1, the matching of m^l fine steps) */
 static void phi_level(orc_mg* mg, int l, const double* in, double* out)
 {
     const orc_scheme* s = mg->s;
     int nx = s->nx;
-    if (mg->p->exact_coarse) {
+    if (l >= 1 && mg->p->coarse_integrator != 0) {
+        long M = 1;
+        for (int j = 0; j < l; ++j) M *= mg->p->m;
+        orc_psi(s, mg->p->coarse_integrator - 1, (int32_t)M, mg->p->dt, in, out);
+    } else if (mg->p->exact_coarse) {
         long reps = 1;
         for (int j = 0; j < l; ++j) reps *= mg->p->m;
         memcpy(out, in, sizeof(double) * (size_t)nx);
@@ -657,8 +736,11 @@ void orc_spatial_operator_vjp(const orc_scheme* s, const double* u, const double
 
 /* lam_out = (dPhi/du (u))^T lam_in for one step of size dt: the stages of eq SSPRK1/2/3
    in reverse order.  lam_out may alias lam_in. */
-void orc_phi_vjp(const orc_scheme* s, double dt, const double* u, const double* lam_in, double* lam_out)
+void orc_phi_vjp(const orc_scheme* s_in, double dt, const double* u, const double* lam_in, double* lam_out)
 {
+    orc_scheme sc = *s_in;
+    if (sc.lf_dx_dt) sc.alpha_fixed = (sc.L / (double)sc.nx) / dt;
+    const orc_scheme* s = &sc;
     int n = s->nx;
     size_t bytes = sizeof(double) * (size_t)n;
     double* A = (double*)malloc(bytes);

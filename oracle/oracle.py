@@ -35,6 +35,8 @@ class Scheme(C.Structure):
         ("eps", C.c_double),
         ("L", C.c_double),
         ("alpha_fixed", C.c_double),
+        ("lf_dx_dt", C.c_int32),
+        ("pad_", C.c_int32),
     ]
 
 
@@ -51,7 +53,7 @@ class Params(C.Structure):
         ("init", C.c_int32),
         ("coarse_guess", C.c_int32),
         ("exact_coarse", C.c_int32),
-        ("pad_", C.c_int32),
+        ("coarse_integrator", C.c_int32),
         ("dt", C.c_double),
         ("tol", C.c_double),
     ]
@@ -84,6 +86,7 @@ def lib():
         L.orc_phi.argtypes = [C.POINTER(Scheme), C.c_double, dp, dp]
         L.orc_phi_lines.argtypes = [C.POINTER(Scheme), C.c_double, dp, dp, C.c_int64]
         L.orc_serial.argtypes = [C.POINTER(Scheme), C.c_double, C.c_int32, dp, dp]
+        L.orc_psi.argtypes = [C.POINTER(Scheme), C.c_int32, C.c_int32, C.c_double, dp, dp]
         L.orc_mgrit.argtypes = [C.POINTER(Scheme), C.POINTER(Params), dp, dp, dp,
                                 C.POINTER(C.c_int32)]
         L.orc_mgrit.restype = C.c_int
@@ -101,16 +104,23 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def scheme(nx, flux=0, k=2, stepper=3, a=1.0, eps=1e-6, L=1.0, alpha_fixed=0.0) -> Scheme:
+def scheme(nx, flux=0, k=2, stepper=3, a=1.0, eps=1e-6, L=1.0, alpha_fixed=0.0, lf_dx_dt=0) -> Scheme:
     return Scheme(flux=flux, k=k, stepper=stepper, nx=nx, a=a, eps=eps, L=L,
-                  alpha_fixed=alpha_fixed)
+                  alpha_fixed=alpha_fixed, lf_dx_dt=lf_dx_dt, pad_=0)
+
+
+def fine_lf_scheme(nx, flux=0, a=1.0, L=1.0) -> Scheme:
+    """The scheme of eq fineLF: first order, forward Euler, alpha_LF = dx/dt."""
+    return scheme(nx, flux=flux, k=0, stepper=1, a=a, L=L, lf_dx_dt=1)
 
 
 def params(nt, dt, m, levels, relax=0, cycle=0, max_iter=100, tol=1e-10, init=0,
-           coarse_guess=0, exact_coarse=0) -> Params:
+           coarse_guess=0, exact_coarse=0, coarse_integrator=0) -> Params:
+    """coarse_integrator: 0 rediscretisation, 1 zeroth-order and 2 first-order
+    fine-integrator matching (sec 3.3.1) on levels >= 1."""
     return Params(nt=nt, m=m, levels=levels, relax=relax, cycle=cycle, max_iter=max_iter,
-                  init=init, coarse_guess=coarse_guess, exact_coarse=exact_coarse, pad_=0,
-                  dt=dt, tol=tol)
+                  init=init, coarse_guess=coarse_guess, exact_coarse=exact_coarse,
+                  coarse_integrator=coarse_integrator, dt=dt, tol=tol)
 
 
 def weno5_candidates(v):
@@ -145,6 +155,15 @@ def phi(s: Scheme, dt, u):
     out = np.zeros_like(u)
     nlines = u.size // s.nx
     lib().orc_phi_lines(C.byref(s), dt, _p(u), _p(out), nlines)
+    return out
+
+
+def psi(s: Scheme, order, M, dt, u):
+    """Coarse integrator matching M fine steps of eq fineLF (fine step dt),
+    order 0 (eq coarseLFord0) or 1 (eq coarseLFord1, eq fineLFxM)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros_like(u)
+    lib().orc_psi(C.byref(s), order, M, dt, _p(u), _p(out))
     return out
 
 

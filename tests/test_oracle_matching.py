@@ -1,0 +1,128 @@
+"""Pins of the fine-integrator-matching coarse integrators (sec 3.3.1) in the
+oracle: the fine scheme is the closed form of eq fineLF; the first-order
+match over two steps differs from two fine steps by exactly the Delta t^2 and
+Delta t^3 terms of the exact expansion (eq fineLFx2, with the factor 1/2 on
+the cubic term that the printed formula drops); for linear advection both
+matches are truncations of the binomial expansion of (E - a dt D)^M; the
+matches have the claimed order in dt for larger M; and MGRIT with them
+reproduces the qualitative findings of sec 4 (rediscretisation diverges,
+first-order matching beats zeroth-order, an F-cycle is steeper)."""
+import numpy as np
+import pytest
+
+from paper_2104_09404_amd import workloads as W
+
+
+def E(v):
+    return 0.5 * (np.roll(v, -1) + np.roll(v, 1))
+
+
+def D(v, dx):
+    return (np.roll(v, -1) - np.roll(v, 1)) / (2 * dx)
+
+
+def test_fine_scheme_is_eq_fineLF(orc):
+    nx = 40
+    u = W.random_lines(3, 1, nx)[0]
+    dx, dt = 1.0 / nx, 0.4 / nx
+    s = orc.fine_lf_scheme(nx)
+    ref = E(u) - dt * D(0.5 * u * u, dx)
+    np.testing.assert_allclose(orc.phi(s, dt, u), ref, rtol=0, atol=1e-15)
+
+
+def test_first_order_match_two_steps_exact_remainder(orc):
+    """Burgers (quadratic flux): Phi(Phi(u)) - Psi1_2(u)
+    = dt^2 D(f'(Eu) Df) - 1/2 dt^3 D(f''(Eu) (Df)^2), f' = u, f'' = 1."""
+    nx = 48
+    dx = 1.0 / nx
+    s = orc.fine_lf_scheme(nx)
+    for seed in range(3):
+        u = W.random_lines(10 + seed, 1, nx)[0]
+        dt = 0.5 * dx / np.max(np.abs(u))
+        two = orc.phi(s, dt, orc.phi(s, dt, u))
+        psi1 = orc.psi(s, 1, 2, dt, u)
+        Df = D(0.5 * u * u, dx)
+        rem = dt ** 2 * D(E(u) * Df, dx) - 0.5 * dt ** 3 * D(Df * Df, dx)
+        np.testing.assert_allclose(two - psi1, rem, rtol=0, atol=1e-14)
+        # the zeroth-order match keeps E^2 u and the rediscretised flux term
+        np.testing.assert_allclose(orc.psi(s, 0, 2, dt, u), E(E(u)) - 2 * dt * Df, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("M", [2, 3, 4, 8])
+def test_linear_advection_binomial_truncation(orc, M):
+    """f = a u: Phi = E - a dt D, so Phi^M = sum_j C(M, j) E^(M-j) (-a dt D)^j;
+    Psi1_M keeps j <= 1 (E^M - M a dt E^(M-1) D), Psi0_M is E^M - M a dt D."""
+    nx, a = 36, 0.8
+    dx = 1.0 / nx
+    dt = 0.3 * dx / a
+    I = np.eye(nx)
+    Em = 0.5 * (np.roll(I, 1, axis=0) + np.roll(I, -1, axis=0))
+    Dm = (np.roll(I, -1, axis=0) - np.roll(I, 1, axis=0)) / (2 * dx)  # (Dm u)_i = (u_{i+1} - u_{i-1})/(2 dx)
+    s = orc.fine_lf_scheme(nx, flux=1, a=a)
+    u = W.random_lines(20 + M, 1, nx)[0]
+    EM = np.linalg.matrix_power(Em, M)
+    ref1 = (EM - M * a * dt * np.linalg.matrix_power(Em, M - 1) @ Dm) @ u
+    ref0 = (EM - M * a * dt * Dm) @ u
+    np.testing.assert_allclose(orc.psi(s, 1, M, dt, u), ref1, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(orc.psi(s, 0, M, dt, u), ref0, rtol=0, atol=1e-13)
+    # and the fine scheme itself composes to the full binomial sum
+    full = np.linalg.matrix_power(Em - a * dt * Dm, M) @ u
+    x = u
+    for _ in range(M):
+        x = orc.phi(s, dt, x)
+    np.testing.assert_allclose(x, full, rtol=0, atol=1e-13)
+
+
+def test_matching_order_in_dt(orc):
+    """Burgers, M = 4: Psi1_M - Phi^M = O(dt^2), Psi0_M - Phi^M = O(dt)."""
+    nx, M = 64, 4
+    dx = 1.0 / nx
+    s = orc.fine_lf_scheme(nx)
+    u = W.random_lines(30, 1, nx)[0]
+    errs = {0: [], 1: []}
+    for dt in (0.2 * dx, 0.1 * dx, 0.05 * dx):
+        x = u
+        for _ in range(M):
+            x = orc.phi(s, dt, x)
+        for order in (0, 1):
+            errs[order].append(np.linalg.norm(orc.psi(s, order, M, dt, u) - x))
+    r0 = [errs[0][i] / errs[0][i + 1] for i in range(2)]
+    r1 = [errs[1][i] / errs[1][i + 1] for i in range(2)]
+    assert all(1.8 < r < 2.2 for r in r0), r0
+    assert all(3.6 < r < 4.4 for r in r1), r1
+
+
+def error_history(orc, u0, coarse_integrator, cycle, iters):
+    nx, nt, T = u0.size, 1024, 0.475
+    dt = T / nt
+    s = orc.fine_lf_scheme(nx)
+    us = orc.serial(s, dt, nt, u0)
+    out = []
+    for k in range(1, iters + 1):
+        p = orc.params(nt, dt, 2, 5, relax=0, cycle=cycle, max_iter=k, tol=-1.0,
+                       coarse_integrator=coarse_integrator)
+        u, hist, it, st = orc.mgrit(s, p, u0)
+        with np.errstate(all="ignore"):
+            out.append(np.linalg.norm(u - us) / np.linalg.norm(us))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("shock", ["stationary", "moving"])
+def test_fine_matching_experiment_qualitative(orc, shock):
+    """sec 4, Fig. MGRITfineMatch: Burgers, N_x = 128, N_T = 1024, T = 0.475,
+    5 levels, m = 2, F-relaxation; u0 = sin(2 pi x) (stationary shock) or
+    (1 + sin(2 pi x))/2 (moving shock).  Rediscretisation blows up; both
+    matching integrators converge, first order below zeroth order; the
+    F-cycle is steeper than the V-cycle.  (The curves themselves are not
+    available: parity of the histories is unpinned.)"""
+    nx = 128
+    base = W.cell_average_sin(nx, 1, 0.0)
+    u0 = base if shock == "stationary" else 0.5 * (1.0 + base)
+    redis = error_history(orc, u0, 0, 0, 3)
+    assert not np.all(np.isfinite(redis)) or redis[-1] > 1.0
+    e0v = error_history(orc, u0, 1, 0, 4)
+    e1v = error_history(orc, u0, 2, 0, 4)
+    e1f = error_history(orc, u0, 2, 1, 4)
+    assert np.all(np.diff(np.log(e0v)) < -1.0) and np.all(np.diff(np.log(e1v)) < -1.0)
+    assert np.all(e1v < e0v)
+    assert np.all(e1f < e1v)
