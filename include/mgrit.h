@@ -69,6 +69,10 @@ enum {
  *   a        advection speed (flux == 1).
  *   eps      WENO epsilon of eq omega (> 0; the paper uses 1e-6).
  *   L        domain length (> 0); dx = L/nx.
+ *   lf_dx_dt 1: the Lax-Friedrichs coefficient is dx/dt of the step being
+ *            taken (with k = 0 and forward Euler this is the scheme of eq
+ *            fineLF, and rediscretised on a coarse level eq coarseLF);
+ *            overrides alpha_fixed.  0: see alpha_fixed.
  *   alpha_fixed  > 0: use this Lax-Friedrichs coefficient; 0: the global
  *            alpha_LF = max over all interfaces and both sides of
  *            |lambda(u^{+-})| of eq eigs, recomputed at every RK stage of every
@@ -85,6 +89,8 @@ typedef struct {
     double eps;
     double L;
     double alpha_fixed;
+    int32_t lf_dx_dt;
+    int32_t pad_;
 } mgrit_scheme;
 
 /*
@@ -108,6 +114,12 @@ typedef struct {
  *   dt        fine step (> 0, finite).
  *   tol       stop when the residual norm is < tol; tol < 0 runs exactly
  *             max_iter cycles.
+ *   coarse_integrator  integrator of the levels l >= 1 (sec 3.3): 0
+ *             rediscretisation (the scheme with step m^l dt); 1 zeroth-order
+ *             (eq coarseLFord0) or 2 first-order (eq coarseLFord1) matching of
+ *             M = m^l steps of the fine scheme (eq fineLFxM), for the fine
+ *             scheme of eq fineLF only (k = 0, stepper 1, lf_dx_dt = 1) and
+ *             lines of at most 4096 cells.
  */
 typedef struct {
     int32_t nt;
@@ -122,6 +134,8 @@ typedef struct {
     int32_t sync_every;
     double dt;
     double tol;
+    int32_t coarse_integrator;
+    int32_t pad2_;
 } mgrit_params;
 
 /*

@@ -260,6 +260,7 @@ int check_scheme(const mgrit_scheme* s)
     if (s->k == 2 && (!(s->eps > 0.0) || !std::isfinite(s->eps))) return fail(MGRIT_EINVAL, "eps must be positive");
     if (s->flux == 1 && !std::isfinite(s->a)) return fail(MGRIT_EINVAL, "advection speed must be finite");
     if (!(s->alpha_fixed >= 0.0) || !std::isfinite(s->alpha_fixed)) return fail(MGRIT_EINVAL, "alpha_fixed must be >= 0");
+    if (s->lf_dx_dt != 0 && s->lf_dx_dt != 1) return fail(MGRIT_EINVAL, "lf_dx_dt must be 0 or 1");
     KernelCfg c;
     int tiles = 0;
     if (!choose_tiled(s->nx, &c, &tiles) && !choose_cfg(s->nx, kLatencyLines, &c))
@@ -273,7 +274,7 @@ int check_dt(double dt)
     return MGRIT_OK;
 }
 
-mgk::PhiConst phi_const(const mgrit_scheme* s)
+mgk::PhiConst phi_const(const mgrit_scheme* s, double dt = 0.0)
 {
     mgk::PhiConst pc;
     if (s->flux == 0) {
@@ -286,6 +287,7 @@ mgk::PhiConst phi_const(const mgrit_scheme* s)
     pc.half_inv_dx = 0.5 / (s->L / (double)s->nx);
     pc.eps = s->eps;
     pc.alpha_fixed = s->alpha_fixed;
+    if (s->lf_dx_dt && dt > 0.0) pc.alpha_fixed = (s->L / (double)s->nx) / dt;
     return pc;
 }
 
@@ -318,8 +320,19 @@ struct Recorded {
 };
 thread_local std::vector<Recorded>* tl_recorder = nullptr;
 
-int launch(int kc, const SweepArgs& a0, const mgrit_scheme* s, hipStream_t st, double phi_lines)
+// the scheme of eq fineLF: the LF coefficient of every step is dx/dt
+void lf_dx_dt_args(SweepArgs& a, const mgrit_scheme* s)
 {
+    if (!s->lf_dx_dt) return;
+    const double dx = s->L / (double)s->nx;
+    a.pc.alpha_fixed = dx / a.dt;
+    if (a.dt_next > 0.0) a.alpha_next = dx / a.dt_next;
+}
+
+int launch(int kc, const SweepArgs& a_in, const mgrit_scheme* s, hipStream_t st, double phi_lines)
+{
+    SweepArgs a0 = a_in;
+    lf_dx_dt_args(a0, s);
     if (tl_recorder != nullptr) {
         tl_recorder->push_back(Recorded{kc, a0, phi_lines});
         return MGRIT_OK;
@@ -460,6 +473,16 @@ int check_params(const mgrit_scheme* s, const mgrit_params* p)
     if (p->storage != 0 && p->storage != 1) return fail(MGRIT_EINVAL, "storage must be 0 or 1");
     if (p->levels == 1 && p->storage != 0) return fail(MGRIT_EINVAL, "levels == 1 needs storage 0");
     if (p->sync_every < 1) return fail(MGRIT_EINVAL, "sync_every must be >= 1");
+    if (p->coarse_integrator < 0 || p->coarse_integrator > 2)
+        return fail(MGRIT_EINVAL, "coarse_integrator must be 0, 1 or 2");
+    if (p->coarse_integrator != 0) {
+        if (s->k != 0 || s->stepper != 1 || s->lf_dx_dt != 1)
+            return fail(MGRIT_EINVAL, "fine-integrator matching needs the scheme of eq fineLF (k = 0, stepper 1, lf_dx_dt 1)");
+        KernelCfg c;
+        int t = 0;
+        if (choose_tiled(s->nx, &c, &t))
+            return fail(MGRIT_EUNSUPPORTED, "fine-integrator matching runs on lines of at most 4096 cells");
+    }
     if (!(p->tol == p->tol)) return fail(MGRIT_EINVAL, "tol is NaN");
     int rc = check_dt(p->dt);
     if (rc) return rc;
@@ -523,6 +546,22 @@ struct Cycle {
     double dtl[16];
     hipStream_t st;
 
+    // fine-integrator matching: matched fine steps M of level l (0: Phi_l)
+    int psiM(int l)
+    {
+        if (l < 1 || p->coarse_integrator == 0) return 0;
+        int M = 1;
+        for (int j = 0; j < l; ++j) M *= p->m;
+        return M;
+    }
+    void psi_args(SweepArgs& a, int l)
+    {
+        a.psi_order = p->coarse_integrator;
+        a.psi_M = psiM(l);
+        a.psi_M_next = psiM(l + 1);
+        a.dt_fine = p->dt;
+    }
+
     double* U(int l) { return l == 0 ? u0_level : (double*)(ws + ly.u_off[l]); }
     double* G(int l) { return l == 0 ? nullptr : (double*)(ws + ly.g_off[l]); }
     double* side() { return (double*)(ws + ly.side_off); }
@@ -535,6 +574,7 @@ struct Cycle {
     int sweep_fc(int l, bool resid)
     {
         SweepArgs a = base_args(s);
+        psi_args(a, l);
         a.nchunks = ly.N[l] / p->m;
         a.m = p->m;
         a.nsteps = p->m - 1;
@@ -556,6 +596,7 @@ struct Cycle {
     int sweep_fr(int l, bool from_side, bool resid)
     {
         SweepArgs a = base_args(s);
+        psi_args(a, l);
         a.nchunks = ly.N[l] / p->m;
         a.m = p->m;
         a.nsteps = p->m - 1;
@@ -589,6 +630,7 @@ struct Cycle {
     int interp(int l, bool relax_f)
     {
         SweepArgs a = base_args(s);
+        psi_args(a, l);
         a.nchunks = ly.N[l] / p->m;
         a.m = p->m;
         a.nsteps = relax_f ? p->m - 1 : 0;
@@ -609,6 +651,7 @@ struct Cycle {
     int coarse(int l)
     {
         SweepArgs a = base_args(s);
+        psi_args(a, l);
         a.nchunks = 1;
         a.m = 0;
         a.nsteps = ly.N[l];
@@ -887,7 +930,7 @@ int mgrit_phi_vjp(const mgrit_scheme* s, double dt, const double* u, const doubl
     a.nsteps = 1;
     a.stored = 0;
     a.dt = dt;
-    a.pc = phi_const(s);
+    a.pc = phi_const(s, dt);
     a.u = u;
     a.lam_in = lam_in;
     a.lam_out = lam_out;
@@ -1002,7 +1045,7 @@ int mgrit_adjoint(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, i
         f.nlines = nb;
         f.nsteps = every;
         f.dt = dt;
-        f.pc = phi_const(s);
+        f.pc = phi_const(s, dt);
         f.u = ckpt + (int64_t)lo * nx;
         f.u_stride = 1;
         f.traj_out = traj;
@@ -1017,7 +1060,7 @@ int mgrit_adjoint(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, i
         r.nsteps = nb * every;
         r.stored = 1;
         r.dt = dt;
-        r.pc = phi_const(s);
+        r.pc = phi_const(s, dt);
         r.traj = traj;
         r.traj_stride = 0;
         r.lam_in = lam_cur;

@@ -58,6 +58,16 @@ struct SweepArgs {
     double* uc_out;
     double* gc_out;
     const int* flag;        // if non-null and *flag != 0 the launch does nothing
+    // fine-integrator matching (first order, forward Euler kernels only): the
+    // steps of this launch apply Psi of order psi_order - 1 matching psi_M fine
+    // steps of size dt_fine instead of Phi (psi_M == 0: Phi), the coarse step
+    // of END_RESTRICT matching psi_M_next steps
+    int psi_order;
+    int psi_M;
+    int psi_M_next;
+    int pad2_;
+    double dt_fine;
+    double alpha_next;      // > 0: LF coefficient of the coarse step of END_RESTRICT
     // lines split over several workgroups (tiled_impl.h)
     int tiles;              // workgroups per line (0: one workgroup per line)
     int groups;             // line groups resident at once (set by the launcher)

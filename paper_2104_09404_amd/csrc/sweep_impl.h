@@ -264,6 +264,93 @@ __device__ __forceinline__ void phi(double (&x)[CPT], double dt, const Geo<CPT, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// fine-integrator matching (sec 3.3.1) for the fine scheme of eq fineLF:
+// average E(v)_i = (v_{i+1} + v_{i-1})/2 and central difference
+// D(v)_i = (v_{i+1} - v_{i-1})/(2 dx) through the LDS line
+// ---------------------------------------------------------------------------
+template <int CPT, int NW, bool RAG>
+__device__ __forceinline__ void lds_neighbours(const double (&v)[CPT], double& nl, double& nr, const Geo<CPT, NW>& g,
+                                               const Smem<CPT, NW>& sm)
+{
+    __syncthreads();  // earlier readers of the line are done
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) sm.line[g.own(q)] = v[q];
+    __syncthreads();
+    nl = sm.line[g.halo[2]];  // cell j0 - 1
+    nr = (RAG && g.ragged) ? sm.line[g.slot(wrapi(g.j0 + g.nvalid, g.nx))] : sm.line[g.halo[3]];
+}
+
+// out = E(v) (avg) or D(v) (diff); out may alias v
+template <int CPT, int NW, bool RAG, bool DIFF>
+__device__ __forceinline__ void ed_op(const double (&v)[CPT], double (&out)[CPT], const Geo<CPT, NW>& g,
+                                      const Smem<CPT, NW>& sm, const PhiConst& pc)
+{
+    double nl, nr;
+    lds_neighbours<CPT, NW, RAG>(v, nl, nr, g, sm);
+    const int last = RAG ? g.nvalid - 1 : CPT - 1;
+    double r[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const double left = (q == 0) ? nl : v[q - 1];
+        const double right = (q == last) ? nr : ((q + 1 < CPT) ? v[q + 1] : nr);
+        r[q] = DIFF ? (right - left) * pc.half_inv_dx : 0.5 * (right + left);
+    }
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) out[q] = r[q];
+}
+
+// x <- Psi(x): the coarse integrator matching M steps of eq fineLF with fine
+// step dt (order 0: eq coarseLFord0, E^M u - M dt D f(u); order 1: eq
+// coarseLFord1 / eq fineLFxM, E^M u - dt sum_{i=1}^{M} E^{i-1} D f(E^{M-i} u),
+// the sum accumulated as T_0 = D f(u), T_k = E T_{k-1} + D f(E^k u))
+template <int CPT, int NW, bool RAG>
+__device__ __forceinline__ void psi(double (&x)[CPT], int order, int M, double dt, const Geo<CPT, NW>& g,
+                                    const Smem<CPT, NW>& sm, const PhiConst& pc)
+{
+    double f[CPT], T[CPT], v[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        v[q] = x[q];
+        f[q] = flux_f(x[q], pc.fa, pc.fb);
+    }
+    ed_op<CPT, NW, RAG, true>(f, T, g, sm, pc);
+    if (order == 0) {
+        for (int r = 0; r < M; ++r) ed_op<CPT, NW, RAG, false>(v, v, g, sm, pc);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) x[q] = v[q] - (double)M * dt * T[q];
+        return;
+    }
+    for (int k = 1; k < M; ++k) {
+        ed_op<CPT, NW, RAG, false>(v, v, g, sm, pc);
+        ed_op<CPT, NW, RAG, false>(T, T, g, sm, pc);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) f[q] = flux_f(v[q], pc.fa, pc.fb);
+        double Df[CPT];
+        ed_op<CPT, NW, RAG, true>(f, Df, g, sm, pc);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) T[q] = T[q] + Df[q];
+    }
+    ed_op<CPT, NW, RAG, false>(v, v, g, sm, pc);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) x[q] = v[q] - dt * T[q];
+}
+
+// one step of the level: Phi, or the matching coarse integrator of M fine steps
+template <int CPT, int NW, int K, int ST, bool RAG>
+__device__ __forceinline__ void level_step(double (&x)[CPT], double dt, int M, const SweepArgs& a,
+                                           const Geo<CPT, NW>& g, const Smem<CPT, NW>& sm, const PhiConst& pc,
+                                           int& par)
+{
+    if constexpr (K == 0 && ST == 1) {
+        if (a.psi_order != 0 && M > 0) {
+            psi<CPT, NW, RAG>(x, a.psi_order - 1, M, a.dt_fine, g, sm, pc);
+            return;
+        }
+    }
+    phi<CPT, NW, K, ST, RAG>(x, dt, g, sm, pc, par);
+}
+
 template <int CPT, int NW>
 __device__ __forceinline__ void load_line(double (&x)[CPT], const double* src, const Geo<CPT, NW>& g)
 {
@@ -367,7 +454,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
 
     const int64_t n0 = (int64_t)c * a.m;
     for (int j = 1; j <= a.nsteps; ++j) {
-        phi<CPT, NW, K, ST, RAG>(x, a.dt, g, sm, a.pc, par);
+        level_step<CPT, NW, K, ST, RAG>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
         if (a.g != nullptr) add_line(x, a.g + (n0 + j) * nx, g);
         if (a.fout != nullptr) {
             if (a.fout_every <= 1) store_line(x, a.fout + (n0 + j) * nx, g);
@@ -377,13 +464,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
 
     if constexpr (END == END_NONE) return;
     if constexpr (END == END_PHI) {
-        phi<CPT, NW, K, ST, RAG>(x, a.dt, g, sm, a.pc, par);
+        level_step<CPT, NW, K, ST, RAG>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
         store_line(x, a.side_out + (int64_t)c * nx, g);
         return;
     }
     // one more step to the chunk's end C-point n1 = (c+1) m
     const int64_t n1 = n0 + a.m;
-    phi<CPT, NW, K, ST, RAG>(x, a.dt, g, sm, a.pc, par);
+    level_step<CPT, NW, K, ST, RAG>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
     if (a.g != nullptr) add_line(x, a.g + n1 * nx, g);
     // the current value at that C-point
     const double* cnext = a.cref + (int64_t)(c + 1) * a.cref_stride * nx;
@@ -405,7 +492,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
     else store_line(x, a.uc_out + (int64_t)(c + 1) * nx, g);
     double y[CPT];
     load_line(y, cstart, g);
-    phi<CPT, NW, K, ST, RAG>(y, a.dt_next, g, sm, a.pc, par);
+    PhiConst pcn = a.pc;
+    if (a.alpha_next > 0.0) pcn.alpha_fixed = a.alpha_next;
+    level_step<CPT, NW, K, ST, RAG>(y, a.dt_next, a.psi_M_next, a, g, sm, pcn, par);
     if (g.active) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) y[q] = x[q] - y[q];

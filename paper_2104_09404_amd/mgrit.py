@@ -48,6 +48,8 @@ class Scheme(C.Structure):
         ("eps", C.c_double),
         ("L", C.c_double),
         ("alpha_fixed", C.c_double),
+        ("lf_dx_dt", C.c_int32),
+        ("pad_", C.c_int32),
     ]
 
 
@@ -67,6 +69,8 @@ class Params(C.Structure):
         ("sync_every", C.c_int32),
         ("dt", C.c_double),
         ("tol", C.c_double),
+        ("coarse_integrator", C.c_int32),
+        ("pad2_", C.c_int32),
     ]
 
 
@@ -163,15 +167,24 @@ def _stream(stream=None) -> Optional[int]:
 
 
 def scheme(nx: int, flux: int = 0, k: int = 2, stepper: int = 3, a: float = 1.0, eps: float = 1e-6,
-           L: float = 1.0, alpha_fixed: float = 0.0) -> Scheme:
-    return Scheme(flux=flux, k=k, stepper=stepper, nx=nx, a=a, eps=eps, L=L, alpha_fixed=alpha_fixed)
+           L: float = 1.0, alpha_fixed: float = 0.0, lf_dx_dt: int = 0) -> Scheme:
+    return Scheme(flux=flux, k=k, stepper=stepper, nx=nx, a=a, eps=eps, L=L, alpha_fixed=alpha_fixed,
+                  lf_dx_dt=lf_dx_dt, pad_=0)
+
+
+def fine_lf_scheme(nx: int, flux: int = 0, a: float = 1.0, L: float = 1.0) -> Scheme:
+    """The scheme of eq fineLF: first order, forward Euler, alpha_LF = dx/dt."""
+    return scheme(nx, flux=flux, k=0, stepper=1, a=a, L=L, lf_dx_dt=1)
 
 
 def params(nt: int, dt: float, m: int, levels: int, relax: int = 1, cycle: int = 0, max_iter: int = 100,
            tol: float = 1e-10, init: int = 0, coarse_guess: int = 0, storage: int = 0,
-           sync_every: int = 1) -> Params:
+           sync_every: int = 1, coarse_integrator: int = 0) -> Params:
+    """coarse_integrator: 0 rediscretisation; 1 / 2 zeroth- / first-order matching
+    of the fine scheme of eq fineLF on levels >= 1 (sec 3.3.1)."""
     return Params(nt=nt, m=m, levels=levels, relax=relax, cycle=cycle, max_iter=max_iter, init=init,
-                  coarse_guess=coarse_guess, storage=storage, sync_every=sync_every, dt=dt, tol=tol)
+                  coarse_guess=coarse_guess, storage=storage, sync_every=sync_every, dt=dt, tol=tol,
+                  coarse_integrator=coarse_integrator, pad2_=0)
 
 
 def scheme_from_problem(pb) -> Scheme:

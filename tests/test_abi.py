@@ -45,14 +45,35 @@ def test_binding_covers_every_declared_symbol():
     assert sorted(mgrit.EXPORTED) == declared_functions()
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the ctypes mirrors equal the C compiler's
+    for include/mgrit.h (a small C program prints them)."""
+    import subprocess
+
     from paper_2104_09404_amd import mgrit
 
-    # mgrit_scheme: 4 int32 + 4 double; mgrit_params: 10 int32 + 2 double
-    assert C.sizeof(mgrit.Scheme) == 48
-    assert C.sizeof(mgrit.Params) == 56
-    assert mgrit.Params.dt.offset == 40
-    assert C.sizeof(mgrit.ProfileEntry) == 32
+    src = tmp_path / "layout.c"
+    checks = {
+        "mgrit_scheme": (mgrit.Scheme, ["flux", "k", "stepper", "nx", "a", "eps", "L", "alpha_fixed", "lf_dx_dt"]),
+        "mgrit_params": (mgrit.Params, ["nt", "m", "levels", "relax", "cycle", "max_iter", "init", "coarse_guess",
+                                        "storage", "sync_every", "dt", "tol", "coarse_integrator"]),
+        "mgrit_profile_entry": (mgrit.ProfileEntry, ["launches", "ms", "phi_lines", "cell_steps"]),
+        "mgrit_problem": (mgrit.Problem, ["scheme", "nt", "dt", "u0", "u"]),
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "%s"' % HEADER, "int main(void) {"]
+    for t, (_, fields) in checks.items():
+        lines.append('printf("%%s %%zu\\n", "%s", sizeof(%s));' % (t, t))
+        for f in fields:
+            lines.append('printf("%%s.%%s %%zu\\n", "%s", "%s", offsetof(%s, %s));' % (t, f, t, f))
+    lines.append("return 0; }")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n") if l)
+    for t, (cls, fields) in checks.items():
+        assert int(out[t]) == C.sizeof(cls), t
+        for f in fields:
+            assert int(out["%s.%s" % (t, f)]) == getattr(cls, f).offset, (t, f)
 
 
 def test_validation_errors_without_gpu(lib):

@@ -1,0 +1,138 @@
+"""GPU parity of the fine-integrator-matching coarse integrators (sec 3.3.1)
+on the fine-matching experiment of sec 4 (Burgers, N_x = 128, N_T = 1024,
+T = 0.475, 5 levels, m = 2): iterates and residual histories against the
+oracle for V- and F-cycles, F- and FCF-relaxation, both matching orders and
+rediscretisation of eq fineLF; convergence to tolerance; batches."""
+import numpy as np
+import pytest
+
+from paper_2104_09404_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2104_09404_amd import mgrit
+
+    mgrit.load()
+    return mgrit
+
+
+def T(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def H(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel_lines(x, ref):
+    x = np.atleast_2d(x)
+    ref = np.atleast_2d(ref)
+    return np.linalg.norm(x - ref, axis=-1) / np.maximum(np.linalg.norm(ref, axis=-1), 1e-300)
+
+
+def initial(shock, nx=128):
+    base = W.cell_average_sin(nx, 1, 0.0)
+    return base if shock == "stationary" else 0.5 * (1.0 + base)
+
+
+NT, TEND = 1024, 0.475
+
+
+def test_fine_lf_step_is_eq_fineLF(gpu):
+    nx = 128
+    u = np.stack([initial("stationary"), initial("moving")])
+    dt = TEND / NT
+    out = T(np.zeros_like(u))
+    gpu.phi(gpu.fine_lf_scheme(nx), dt, T(u), out)
+    E = 0.5 * (np.roll(u, -1, axis=1) + np.roll(u, 1, axis=1))
+    D = (np.roll(0.5 * u * u, -1, axis=1) - np.roll(0.5 * u * u, 1, axis=1)) * nx / 2
+    np.testing.assert_allclose(H(out), E - dt * D, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("shock", ["stationary", "moving"])
+@pytest.mark.parametrize("ci", [1, 2])
+@pytest.mark.parametrize("relax,cycle", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_matching_cycles_vs_oracle(orc, gpu, shock, ci, relax, cycle):
+    nx = 128
+    u0 = initial(shock)
+    dt = TEND / NT
+    so = orc.fine_lf_scheme(nx)
+    po = orc.params(NT, dt, 2, 5, relax=relax, cycle=cycle, max_iter=3, tol=-1.0, coarse_integrator=ci)
+    uo, ho, no, sto = orc.mgrit(so, po, u0)
+    sg = gpu.fine_lf_scheme(nx)
+    pg = gpu.params(NT, dt, 2, 5, relax=relax, cycle=cycle, max_iter=3, tol=-1.0, coarse_integrator=ci,
+                    sync_every=3)
+    ug = T(np.zeros((NT + 1, nx)))
+    rc, hg, ng = gpu.cycle(sg, pg, T(u0), ug)
+    assert ng == no == 3
+    assert np.all(rel_lines(H(ug), uo) < TOL), rel_lines(H(ug), uo).max()
+    # residual norms: relative 1e-9, with a round-off floor of 1e-13 x the
+    # norm of the C-point lines
+    np.testing.assert_allclose(hg, ho, rtol=1e-9, atol=1e-13 * np.linalg.norm(u0) * np.sqrt(NT / 2))
+
+
+def test_rediscretisation_first_cycle_vs_oracle(orc, gpu):
+    """eq coarseLF on the coarse levels (alpha = dx/dt_l): one V-cycle, before
+    the iterates blow up."""
+    nx = 128
+    u0 = initial("stationary")
+    dt = TEND / NT
+    uo, ho, no, sto = orc.mgrit(orc.fine_lf_scheme(nx), orc.params(NT, dt, 2, 5, max_iter=1, tol=-1.0), u0)
+    ug = T(np.zeros((NT + 1, nx)))
+    rc, hg, ng = gpu.cycle(gpu.fine_lf_scheme(nx), gpu.params(NT, dt, 2, 5, relax=0, max_iter=1, tol=-1.0), T(u0), ug)
+    assert np.all(rel_lines(H(ug), uo) < TOL)
+    np.testing.assert_allclose(hg, ho, rtol=1e-9, atol=1e-13 * np.linalg.norm(u0) * np.sqrt(NT / 2))
+
+
+@pytest.mark.parametrize("ci", [1, 2])
+def test_matching_converges_to_serial(orc, gpu, ci):
+    """F-cycle, F-relaxation, tol 1e-10 on the residual: same iteration count
+    as the oracle, and the converged iterate is the serial solution."""
+    nx = 128
+    u0 = initial("moving")
+    dt = TEND / NT
+    po = orc.params(NT, dt, 2, 5, relax=0, cycle=1, max_iter=40, tol=1e-10, coarse_integrator=ci)
+    uo, ho, no, sto = orc.mgrit(orc.fine_lf_scheme(nx), po, u0)
+    pg = gpu.params(NT, dt, 2, 5, relax=0, cycle=1, max_iter=40, tol=1e-10, coarse_integrator=ci)
+    ug = T(np.zeros((NT + 1, nx)))
+    rc, hg, ng = gpu.cycle(gpu.fine_lf_scheme(nx), pg, T(u0), ug)
+    assert rc == gpu.MGRIT_OK and sto == 0 and ng == no
+    us = orc.serial(orc.fine_lf_scheme(nx), dt, NT, u0)
+    assert np.all(rel_lines(H(ug), us) < 1e-9)
+
+
+def test_matching_in_batches(gpu):
+    """Stationary and moving shocks at two resolutions in one batch: bitwise
+    equal to their own solves."""
+    dt_of = {}
+    probs = []
+    for nx, nt in ((128, 1024), (256, 2048)):
+        for shock in ("stationary", "moving"):
+            probs.append((gpu.fine_lf_scheme(nx), nt, TEND / nt, initial(shock, nx)))
+    p = gpu.params(0, 0.0, 2, 5, relax=0, cycle=1, max_iter=4, tol=-1.0, coarse_integrator=2, sync_every=4)
+    us, table = [], []
+    for sch, nt, dt, u0 in probs:
+        u = T(np.zeros((nt + 1, sch.nx)))
+        us.append(u)
+        table.append((sch, nt, dt, T(u0), u))
+    hs, its, sts = gpu.cycle_batched(table, p)
+    for i, (sch, nt, dt, u0) in enumerate(probs):
+        q = gpu.params(nt, dt, 2, 5, relax=0, cycle=1, max_iter=4, tol=-1.0, coarse_integrator=2, sync_every=4)
+        u1 = T(np.zeros((nt + 1, sch.nx)))
+        rc, h1, n1 = gpu.cycle(sch, q, T(u0), u1)
+        assert np.array_equal(H(us[i]), H(u1))
+        np.testing.assert_allclose(hs[i], h1, rtol=1e-13)

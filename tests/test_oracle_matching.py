@@ -126,3 +126,25 @@ def test_fine_matching_experiment_qualitative(orc, shock):
     assert np.all(np.diff(np.log(e0v)) < -1.0) and np.all(np.diff(np.log(e1v)) < -1.0)
     assert np.all(e1v < e0v)
     assert np.all(e1f < e1v)
+
+
+@pytest.mark.parametrize("relax", [0, 1])
+def test_restriction_guess_qualitative(orc, relax):
+    """sec 4, Fig. MGRITrestrictionGuess (stationary shock, zeroth-order
+    matching, V-cycle, N_x = 128, N_T = 1024): the coarse guess of eq
+    restriction::u gives a better or comparable error than injection."""
+    nx, nt, T = 128, 1024, 0.475
+    dt = T / nt
+    u0 = W.cell_average_sin(nx, 1, 0.0)
+    s = orc.fine_lf_scheme(nx)
+    us = orc.serial(s, dt, nt, u0)
+    errs = {}
+    for guess in (0, 1):
+        e = []
+        for k in range(1, 5):
+            p = orc.params(nt, dt, 2, 5, relax=relax, cycle=0, max_iter=k, tol=-1.0, coarse_guess=guess,
+                           coarse_integrator=1)
+            u, hist, it, st = orc.mgrit(s, p, u0)
+            e.append(np.linalg.norm(u - us) / np.linalg.norm(us))
+        errs[guess] = np.array(e)
+    assert np.all(errs[0] <= 1.5 * errs[1]), errs
