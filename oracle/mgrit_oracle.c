@@ -19,6 +19,7 @@
  *   A(u)_i = -(F_{i+1/2} - F_{i-1/2}) / dx               (eq spaceDisc)
  *   WENO reconstruction of u^-_{i+1/2}, u^+_{i+1/2}      (sec 2.1.1, eq C, B, omega, D)
  *   Lax-Friedrichs flux with global alpha_LF             (sec 2.1.2, eq LFflux, eigs)
+ *   Roe flux with the Harten-Hyman entropy fix           (sec 2.1.3, eq roeflux)
  *   Phi = SSPRK3 / SSPRK2 / forward Euler                (sec 2.2, eq SSPRK3/2/1)
  *   MGRIT: F/FCF relaxation, FAS restriction, coarse     (sec 3.2, eq relaxation,
  *   solve, ideal interpolation, V- and F-cycles           restrictionOperator, FAScorrection,
@@ -32,6 +33,9 @@
  *       which the printed c, d and B tables give a fifth-order scheme
  *       (the text of sec 2.1.1 states {i+r-k, ..., i+r}).
  *   R2  B_r is (k+1)x(k+1) and q is in R^(k+1) (the printed matrices are 3x3).
+ *   R15 For k != 2 the tables are derived from the definitions behind eq C, B
+ *       and D (see the WENO section below); the derivation reproduces the
+ *       printed k = 2 tables.
  *   R3  The dissipative term of the LF flux carries a MINUS sign (with a plus
  *       the flux is anti-diffusive; with minus, k=0, alpha=dx/dt and forward
  *       Euler reproduce eq fineLF exactly, as sec 3.3.1 states).
@@ -47,6 +51,12 @@
  *   R10 Stopping norm: Euclidean norm of the level-0 C-point residual over all
  *       C-points and cells, r^{mi} = Phi_0(u^{mi-1}) + g^{mi} - u^{mi},
  *       evaluated on the current iterate after an F-relaxation.
+ *   R16 Roe flux: F = (f(u-) + f(u+))/2 - (1/2) sum_k q_H(lambda_k) alpha_k r_k,
+ *       q_H = (lambda^2/delta + delta)/2 inside the fix, alpha_k the jump of
+ *       the k-th characteristic variable (for one equation: u+ - u-).  The
+ *       printed formula has no 1/2 on the sum and lambda/delta in q_H; with
+ *       the 1/2 and lambda^2 it is the textbook scheme, which is upwind for
+ *       Burgers (as printed it is not).
  */
 #include <math.h>
 #include <stdint.h>
@@ -59,7 +69,8 @@
 
 typedef struct {
     int32_t flux;        /* 0: Burgers f(u) = u^2/2 (eq burgers); 1: linear advection f(u) = a u */
-    int32_t k;           /* WENO polynomial degree: 0 (piecewise constant) or 2 (WENO5)          */
+    int32_t k;           /* WENO polynomial degree k, order s = 2k+1: 0 (piecewise constant),    */
+                         /* 1 (WENO3), 2 (WENO5), 3 (WENO7)                                      */
     int32_t stepper;     /* 1: forward Euler (eq SSPRK1), 2: SSPRK2, 3: SSPRK3                  */
     int32_t nx;          /* number of cells N_x                                                 */
     double  a;           /* advection speed (flux == 1)                                          */
@@ -68,7 +79,8 @@ typedef struct {
     double  alpha_fixed; /* > 0: use this value as alpha_LF instead of the global maximum       */
     int32_t lf_dx_dt;    /* 1: alpha_LF = dx/dt of the step taken (eq fineLF, and eq coarseLF     */
                          /*    when rediscretised); overrides alpha_fixed                         */
-    int32_t pad_;
+    int32_t numflux;     /* 0: Lax-Friedrichs (eq LFflux); 1: Roe with the Harten-Hyman fix       */
+                         /*    (eq roeflux, reading R16); alpha_fixed and lf_dx_dt do not apply   */
 } orc_scheme;
 
 typedef struct {
@@ -172,14 +184,196 @@ double orc_weno5_left(const double* v, double eps)
     return out;
 }
 
+/* ------------------------------------------------------------------------ */
+/* WENO reconstruction of any degree k (sec 2.1.1)                            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Only k = 2 has printed tables.  For the other degrees (s = 2k+1 = 1, 3, 7)
+ * the tables are computed from what defines them, in units dx = 1, with the
+ * reconstruction cell i = [-1/2, 1/2] and its right interface at x = 1/2:
+ *   eq C: the polynomial of degree k whose averages over the k+1 cells of
+ *         stencil r (cells i-r+j, j = 0..k; reading R1) equal q_j, evaluated
+ *         at 1/2:  c_r = e^T M_r^{-1},  M_r[j][n] = average of x^n over cell
+ *         j - r,  e_n = (1/2)^n;
+ *   eq B: beta_r = sum_{l=1..k} int_{-1/2}^{1/2} (d^l p/dx^l)^2 dx = q^T B_r q
+ *         with B_r = M_r^{-T} G M_r^{-1},  G[n][n'] = sum_l int (d^l x^n)(d^l x^n')
+ *         (with dx = 1 the weights dx^{2l-1} are 1: they make beta scale-free);
+ *   eq D: the d_r for which sum_r d_r c_r, placed on the 2k+1 cells i-k..i+k,
+ *         equals the interface value of the degree-2k polynomial through all
+ *         of them (order s = 2k+1), solved cell by cell from the left end of
+ *         the big stencil, which only stencil r = k reaches.
+ */
+#define ORC_KMAX 3
+
+typedef struct {
+    int ready;
+    double c[ORC_KMAX + 1][ORC_KMAX + 1];
+    double d[ORC_KMAX + 1];
+    double B[ORC_KMAX + 1][ORC_KMAX + 1][ORC_KMAX + 1];
+} orc_weno_tab;
+
+/* int_{o-1/2}^{o+1/2} x^n dx */
+static long double cell_moment(int o, int n)
+{
+    return (powl(o + 0.5L, n + 1) - powl(o - 0.5L, n + 1)) / (long double)(n + 1);
+}
+
+/* inverse of the n x n matrix a (row major) by Gauss-Jordan elimination with
+   partial pivoting; a is overwritten.  The tables are derived in long double
+   and rounded once to double. */
+static void mat_inverse(int n, long double* a, long double* inv)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) inv[i * n + j] = (i == j) ? 1.0 : 0.0;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int i = col + 1; i < n; ++i)
+            if (fabsl(a[i * n + col]) > fabsl(a[piv * n + col])) piv = i;
+        for (int j = 0; j < n; ++j) {
+            long double t = a[col * n + j];
+            a[col * n + j] = a[piv * n + j];
+            a[piv * n + j] = t;
+            t = inv[col * n + j];
+            inv[col * n + j] = inv[piv * n + j];
+            inv[piv * n + j] = t;
+        }
+        long double p = a[col * n + col];
+        for (int j = 0; j < n; ++j) {
+            a[col * n + j] /= p;
+            inv[col * n + j] /= p;
+        }
+        for (int i = 0; i < n; ++i) {
+            if (i == col) continue;
+            long double f = a[i * n + col];
+            for (int j = 0; j < n; ++j) {
+                a[i * n + j] -= f * a[col * n + j];
+                inv[i * n + j] -= f * inv[col * n + j];
+            }
+        }
+    }
+}
+
+/* interface values at x = 1/2 of the degree-(ncell-1) polynomial whose
+   averages over the cells first_cell .. first_cell+ncell-1 are given:
+   coef[j] such that p(1/2) = sum_j coef[j] q_j; minv receives M^{-1} */
+static void interface_weights(int first_cell, int ncell, long double* coef, long double* minv)
+{
+    long double M[2 * ORC_KMAX + 1][2 * ORC_KMAX + 1];
+    for (int j = 0; j < ncell; ++j)
+        for (int n = 0; n < ncell; ++n) M[j][n] = cell_moment(first_cell + j, n);
+    long double a[(2 * ORC_KMAX + 1) * (2 * ORC_KMAX + 1)];
+    for (int j = 0; j < ncell; ++j)
+        for (int n = 0; n < ncell; ++n) a[j * ncell + n] = M[j][n];
+    mat_inverse(ncell, a, minv);
+    for (int j = 0; j < ncell; ++j) {
+        long double acc = 0.0L;
+        for (int n = 0; n < ncell; ++n) acc += powl(0.5L, n) * minv[n * ncell + j];
+        coef[j] = acc;
+    }
+}
+
+/* n! / (n-l)!  (the factor of d^l x^n / dx^l = n!/(n-l)! x^(n-l)) */
+static long double falling(int n, int l)
+{
+    long double f = 1.0L;
+    for (int i = 0; i < l; ++i) f *= (long double)(n - i);
+    return f;
+}
+
+static orc_weno_tab g_weno_tab[ORC_KMAX + 1];
+
+static const orc_weno_tab* weno_tab(int k)
+{
+    orc_weno_tab* t = &g_weno_tab[k];
+    if (t->ready) return t;
+    int n1 = k + 1;
+    /* G[n][n'] = sum_{l=1..k} int_{-1/2}^{1/2} (d^l x^n)(d^l x^n') dx */
+    long double G[ORC_KMAX + 1][ORC_KMAX + 1];
+    for (int n = 0; n < n1; ++n)
+        for (int m = 0; m < n1; ++m) {
+            long double acc = 0.0L;
+            for (int l = 1; l <= k; ++l)
+                if (n >= l && m >= l) acc += falling(n, l) * falling(m, l) * cell_moment(0, n + m - 2 * l);
+            G[n][m] = acc;
+        }
+    long double c[ORC_KMAX + 1][ORC_KMAX + 1], d[ORC_KMAX + 1];
+    for (int r = 0; r <= k; ++r) {
+        long double minv[(ORC_KMAX + 1) * (ORC_KMAX + 1)];
+        interface_weights(-r, n1, c[r], minv);
+        /* B_r = M_r^{-T} G M_r^{-1} */
+        for (int a = 0; a < n1; ++a)
+            for (int b = 0; b < n1; ++b) {
+                long double acc = 0.0L;
+                for (int n = 0; n < n1; ++n)
+                    for (int m = 0; m < n1; ++m) acc += minv[n * n1 + a] * G[n][m] * minv[m * n1 + b];
+                t->B[r][a][b] = (double)acc;
+            }
+    }
+    /* eq D: big stencil i-k..i+k */
+    long double cbig[2 * ORC_KMAX + 1];
+    long double minv_big[(2 * ORC_KMAX + 1) * (2 * ORC_KMAX + 1)];
+    interface_weights(-k, 2 * k + 1, cbig, minv_big);
+    /* window position p (cell i-k+p) is reached by the stencils r >= k-p, at
+       their cell j = p-k+r */
+    for (int p = 0; p <= k; ++p) {
+        long double acc = cbig[p];
+        for (int r = k - p + 1; r <= k; ++r) acc -= d[r] * c[r][p - k + r];
+        d[k - p] = acc / c[k - p][0];
+    }
+    for (int r = 0; r <= k; ++r) {
+        t->d[r] = (double)d[r];
+        for (int j = 0; j <= k; ++j) t->c[r][j] = (double)c[r][j];
+    }
+    t->ready = 1;
+    return t;
+}
+
+/* the tables of degree k (0..3) computed as above: c[(k+1)(k+1)], d[k+1], B[(k+1)^3] */
+void orc_weno_tables(int32_t k, double* c, double* d, double* B)
+{
+    const orc_weno_tab* t = weno_tab(k);
+    int n1 = k + 1;
+    for (int r = 0; r < n1; ++r) {
+        d[r] = t->d[r];
+        for (int j = 0; j < n1; ++j) c[r * n1 + j] = t->c[r][j];
+        for (int a = 0; a < n1; ++a)
+            for (int b = 0; b < n1; ++b) B[(r * n1 + a) * n1 + b] = t->B[r][a][b];
+    }
+}
+
+/* q^-_{i+1/2} of degree k from v[0..2k] = q_{i-k}, ..., q_{i+k} (eq C, B, omega
+   and the convex combination); k = 2 uses the printed tables */
+double orc_weno_left(int32_t k, const double* v, double eps)
+{
+    if (k == 2) return orc_weno5_left(v, eps);
+    const orc_weno_tab* t = weno_tab(k);
+    double p[ORC_KMAX + 1], alpha[ORC_KMAX + 1];
+    double sum = 0.0;
+    for (int r = 0; r <= k; ++r) {
+        const double* q = v + k - r; /* stencil r: cells i-r .. i-r+k */
+        double acc = 0.0;
+        for (int j = 0; j <= k; ++j) acc += t->c[r][j] * q[j];
+        p[r] = acc;
+        double beta = 0.0;
+        for (int a = 0; a <= k; ++a)
+            for (int b = 0; b <= k; ++b) beta += q[a] * t->B[r][a][b] * q[b];
+        alpha[r] = t->d[r] / ((eps + beta) * (eps + beta));
+        sum += alpha[r];
+    }
+    double out = 0.0;
+    for (int r = 0; r <= k; ++r) out += (alpha[r] / sum) * p[r];
+    return out;
+}
+
 /* u^-_{i+1/2}: reconstruction in cell i at its right interface */
 static double recon_minus(const orc_scheme* s, const double* u, int i)
 {
     int n = s->nx;
     if (s->k == 0) return u[wrap(i, n)];
-    double v[5];
-    for (int j = 0; j < 5; ++j) v[j] = u[wrap(i - 2 + j, n)];
-    return orc_weno5_left(v, s->eps);
+    double v[2 * ORC_KMAX + 1];
+    for (int j = 0; j <= 2 * s->k; ++j) v[j] = u[wrap(i - s->k + j, n)];
+    return orc_weno_left(s->k, v, s->eps);
 }
 
 /* u^+_{i+1/2}: the mirror-image reconstruction in cell i+1 at its left interface (sec 2.1.1) */
@@ -187,16 +381,39 @@ static double recon_plus(const orc_scheme* s, const double* u, int i)
 {
     int n = s->nx;
     if (s->k == 0) return u[wrap(i + 1, n)];
-    double v[5];
-    for (int j = 0; j < 5; ++j) v[j] = u[wrap(i + 3 - j, n)];
-    return orc_weno5_left(v, s->eps);
+    double v[2 * ORC_KMAX + 1];
+    for (int j = 0; j <= 2 * s->k; ++j) v[j] = u[wrap(i + 1 + s->k - j, n)];
+    return orc_weno_left(s->k, v, s->eps);
 }
 
 /* ------------------------------------------------------------------------ */
-/* Semi-discrete operator A(u) (eq spaceDisc) with the LF flux (eq LFflux)   */
+/* Roe flux with the Harten-Hyman entropy fix (sec 2.1.3, eq roeflux)         */
 /* ------------------------------------------------------------------------ */
 
-/* A[i] = -(F_{i+1/2} - F_{i-1/2})/dx.  Returns the alpha_LF used.  */
+/* For one equation (D = 1) the Jacobian has the single eigenvalue
+   lambda = f'(u) and eigenvector r = 1, so alpha_0 = (u+ - u-) r.  The Roe
+   average of Burgers is u_hat = (u+ + u-)/2 (its eigenvalue is u_hat); the
+   Jacobian of advection is the constant a.  Reading R16 for the 1/2 and q_H; for advection
+   lambda_hat = a and delta = 0, so q_H = |a| (reading R17). */
+double orc_roe_flux(const orc_scheme* s, double um, double up)
+{
+    double lam_m = flux_lambda(s, um);
+    double lam_p = flux_lambda(s, up);
+    double lam_hat = (s->flux == 0) ? (up + um) / 2.0 : s->a;
+    double r_hat = 1.0;
+    double alpha = (up - um) * r_hat;
+    double delta = fmax(0.0, fmax(lam_hat - lam_m, lam_p - lam_hat));
+    double qH;
+    if (fabs(lam_hat) < delta) qH = 0.5 * (lam_hat * lam_hat / delta + delta);
+    else qH = fabs(lam_hat);
+    return 0.5 * (flux_f(s, um) + flux_f(s, up)) - 0.5 * qH * alpha * r_hat;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Semi-discrete operator A(u) (eq spaceDisc), LF or Roe flux                */
+/* ------------------------------------------------------------------------ */
+
+/* A[i] = -(F_{i+1/2} - F_{i-1/2})/dx.  Returns the alpha_LF used (0 with the Roe flux).  */
 double orc_spatial_operator(const orc_scheme* s, const double* u, double* A)
 {
     int n = s->nx;
@@ -209,6 +426,14 @@ double orc_spatial_operator(const orc_scheme* s, const double* u, double* A)
         up[i] = recon_plus(s, u, i);
     }
     double alpha;
+    if (s->numflux == 1) {
+        for (int i = 0; i < n; ++i) F[i] = orc_roe_flux(s, um[i], up[i]);
+        for (int i = 0; i < n; ++i) A[i] = -(F[i] - F[wrap(i - 1, n)]) / dx;
+        free(um);
+        free(up);
+        free(F);
+        return 0.0;
+    }
     if (s->alpha_fixed > 0.0) {
         alpha = s->alpha_fixed;
     } else {
@@ -360,7 +585,8 @@ void orc_psi(const orc_scheme* s, int32_t order, int32_t M, double dt, const dou
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    const orc_scheme* s;
+    const orc_scheme* s;      /* level 0 (nx, L and the PDE are common to all levels) */
+    const orc_scheme* sl[32]; /* the scheme of level l (E5: the order may change per level) */
     const orc_params* p;
     int L;               /* number of levels */
     int nsteps[32];      /* N_l */
@@ -378,7 +604,7 @@ static double* node(double* base, int n, int nx) { return base + (size_t)n * (si
    sec 3.3.1, the matching of m^l fine steps) */
 static void phi_level(orc_mg* mg, int l, const double* in, double* out)
 {
-    const orc_scheme* s = mg->s;
+    const orc_scheme* s = mg->sl[l];
     int nx = s->nx;
     if (l >= 1 && mg->p->coarse_integrator != 0) {
         long M = 1;
@@ -527,7 +753,9 @@ static void fcycle(orc_mg* mg, int l)
 }
 
 /*
- * Multilevel FAS-MGRIT.
+ * Multilevel FAS-MGRIT with the scheme schemes[l] on level l (they share nx, L
+ * and the PDE; the reconstruction degree, Runge-Kutta scheme and numerical
+ * flux may differ per level, as in Fig. MGRITweno_diffOrd).
  *   u0       [nx]               initial condition (g^0 of eq monolithicSystem)
  *   u        [(nt+1) x nx]      in: initial iterate if p->init == 1; out: final iterate
  *   res_hist [max_iter + 1]     ||r_k||, the residual of the iterate after k cycles
@@ -538,12 +766,14 @@ static void fcycle(orc_mg* mg, int l)
  * levels == 1 is serial time stepping (the coarse solve on level 0); then
  * res_hist[0] = 0, iters = 1.
  */
-int orc_mgrit(const orc_scheme* s, const orc_params* p, const double* u0, double* u,
-              double* res_hist, int32_t* iters)
+int orc_mgrit_levels(const orc_scheme* schemes, const orc_params* p, const double* u0, double* u,
+                     double* res_hist, int32_t* iters)
 {
     orc_mg mg;
     memset(&mg, 0, sizeof(mg));
+    const orc_scheme* s = &schemes[0];
     mg.s = s;
+    for (int l = 0; l < p->levels && l < 32; ++l) mg.sl[l] = &schemes[l];
     mg.p = p;
     mg.L = p->levels;
     int nx = s->nx;
@@ -610,6 +840,15 @@ int orc_mgrit(const orc_scheme* s, const orc_params* p, const double* u0, double
     return status;
 }
 
+/* one scheme on every level (rediscretisation with dt_l = m^l dt) */
+int orc_mgrit(const orc_scheme* s, const orc_params* p, const double* u0, double* u,
+              double* res_hist, int32_t* iters)
+{
+    orc_scheme sl[32];
+    for (int l = 0; l < p->levels && l < 32; ++l) sl[l] = *s;
+    return orc_mgrit_levels(sl, p, u0, u, res_hist, iters);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Discrete adjoint of Phi and of serial time stepping                        */
 /* (not in the paper: the derivative of the scheme above, written by hand)    */
@@ -673,6 +912,11 @@ void orc_spatial_operator_vjp(const orc_scheme* s, const double* u, const double
 {
     int n = s->nx;
     double dx = s->L / (double)n;
+    if ((s->k != 0 && s->k != 2) || s->numflux != 0) {
+        /* only WENO5 / first order with the LF flux are differentiated here */
+        for (int i = 0; i < n; ++i) out[i] = NAN;
+        return;
+    }
     double* um = (double*)malloc(sizeof(double) * (size_t)n);
     double* up = (double*)malloc(sizeof(double) * (size_t)n);
     for (int i = 0; i < n; ++i) {

@@ -36,7 +36,7 @@ class Scheme(C.Structure):
         ("L", C.c_double),
         ("alpha_fixed", C.c_double),
         ("lf_dx_dt", C.c_int32),
-        ("pad_", C.c_int32),
+        ("numflux", C.c_int32),
     ]
 
 
@@ -90,6 +90,14 @@ def lib():
         L.orc_mgrit.argtypes = [C.POINTER(Scheme), C.POINTER(Params), dp, dp, dp,
                                 C.POINTER(C.c_int32)]
         L.orc_mgrit.restype = C.c_int
+        L.orc_mgrit_levels.argtypes = [C.POINTER(Scheme), C.POINTER(Params), dp, dp, dp,
+                                       C.POINTER(C.c_int32)]
+        L.orc_mgrit_levels.restype = C.c_int
+        L.orc_weno_tables.argtypes = [C.c_int32, dp, dp, dp]
+        L.orc_weno_left.argtypes = [C.c_int32, dp, C.c_double]
+        L.orc_weno_left.restype = C.c_double
+        L.orc_roe_flux.argtypes = [C.POINTER(Scheme), C.c_double, C.c_double]
+        L.orc_roe_flux.restype = C.c_double
         L.orc_weno5_left_grad.argtypes = [dp, C.c_double, dp]
         L.orc_spatial_operator_vjp.argtypes = [C.POINTER(Scheme), dp, dp, dp]
         L.orc_phi_vjp.argtypes = [C.POINTER(Scheme), C.c_double, dp, dp, dp]
@@ -104,9 +112,12 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def scheme(nx, flux=0, k=2, stepper=3, a=1.0, eps=1e-6, L=1.0, alpha_fixed=0.0, lf_dx_dt=0) -> Scheme:
+def scheme(nx, flux=0, k=2, stepper=3, a=1.0, eps=1e-6, L=1.0, alpha_fixed=0.0, lf_dx_dt=0,
+           numflux=0) -> Scheme:
+    """k: WENO degree (order s = 2k+1); numflux 0 Lax-Friedrichs, 1 Roe with
+    the Harten-Hyman fix (sec 2.1.3)."""
     return Scheme(flux=flux, k=k, stepper=stepper, nx=nx, a=a, eps=eps, L=L,
-                  alpha_fixed=alpha_fixed, lf_dx_dt=lf_dx_dt, pad_=0)
+                  alpha_fixed=alpha_fixed, lf_dx_dt=lf_dx_dt, numflux=numflux)
 
 
 def fine_lf_scheme(nx, flux=0, a=1.0, L=1.0) -> Scheme:
@@ -140,6 +151,27 @@ def weno5_beta(v):
 def weno5_left(v, eps=1e-6):
     v = np.ascontiguousarray(v, dtype=np.float64)
     return lib().orc_weno5_left(_p(v), eps)
+
+
+def weno_tables(k):
+    """(c [k+1, k+1], d [k+1], B [k+1, k+1, k+1]) of degree k, computed from
+    their definitions (eq C, B, D)."""
+    n1 = k + 1
+    c, d, B = np.zeros((n1, n1)), np.zeros(n1), np.zeros((n1, n1, n1))
+    lib().orc_weno_tables(k, _p(c), _p(d), _p(B))
+    return c, d, B
+
+
+def weno_left(k, v, eps=1e-6):
+    """u^-_{i+1/2} of degree k from v = u_{i-k} .. u_{i+k}."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.size == 2 * k + 1
+    return lib().orc_weno_left(k, _p(v), eps)
+
+
+def roe_flux(s: Scheme, um, up):
+    """Roe flux with the Harten-Hyman fix at one interface (eq roeflux)."""
+    return lib().orc_roe_flux(C.byref(s), float(um), float(up))
 
 
 def spatial_operator(s: Scheme, u):
@@ -183,6 +215,22 @@ def mgrit(s: Scheme, p: Params, u0, u_init=None):
     hist = np.full(p.max_iter + 1, np.nan)
     iters = C.c_int32(0)
     st = lib().orc_mgrit(C.byref(s), C.byref(p), _p(u0), _p(u), _p(hist), C.byref(iters))
+    n = iters.value
+    return u, hist[: n + 1] if p.levels > 1 else hist[:1], n, st
+
+
+def mgrit_levels(schemes, p: Params, u0, u_init=None):
+    """FAS-MGRIT with schemes[l] on level l; returns as :func:`mgrit`."""
+    assert len(schemes) == p.levels
+    arr = (Scheme * len(schemes))(*schemes)
+    nx = schemes[0].nx
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    u = np.zeros((p.nt + 1, nx))
+    if u_init is not None:
+        u[...] = u_init
+    hist = np.full(p.max_iter + 1, np.nan)
+    iters = C.c_int32(0)
+    st = lib().orc_mgrit_levels(arr, C.byref(p), _p(u0), _p(u), _p(hist), C.byref(iters))
     n = iters.value
     return u, hist[: n + 1] if p.levels > 1 else hist[:1], n, st
 

@@ -19,6 +19,10 @@ sizes of the five benchmark configurations:
   W2  burgers_weno5_nx65536     WENO5 + SSPRK3, 4-level FCF V-cycle, large single problem
   W3  batched_512               512 independent Burgers / advection problems
   W4  adjoint_nx4096            WENO5 + SSPRK3 forward for the discrete adjoint
+
+and the settings of the paper's own high-order experiment (Fig. MGRITweno):
+
+  E4  e4_burgers_s{1,3,5,7}_{lf,roe}  N_x = 64, N_T = 400, 3-level V-cycle, m = 2
 """
 from __future__ import annotations
 
@@ -40,7 +44,7 @@ class Problem:
 
     name: str
     flux: int              # 0 Burgers, 1 linear advection
-    k: int                 # 0 first order, 2 WENO5
+    k: int                 # WENO degree, order s = 2k+1 (0 first order, 2 WENO5)
     stepper: int           # 1 FE, 2 SSPRK2, 3 SSPRK3
     nx: int
     nt: int
@@ -55,6 +59,7 @@ class Problem:
     tol: float = 1e-10
     max_iter: int = 100
     cfl: Optional[float] = None
+    numflux: int = 0       # 0 Lax-Friedrichs, 1 Roe with the Harten-Hyman fix
     extra: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -184,6 +189,21 @@ def w4_adjoint(nx: int = 4096, nt: int = 2048, ndirs: int = 16) -> Problem:
     p.extra["directions"] = dirs
     p.extra["checkpoint_every"] = 32
     return p
+
+
+def e4_high_order(k: int = 2, numflux: int = 0, stepper: int = 3, max_iter: int = 20) -> Problem:
+    """The high-order experiment of Fig. MGRITweno for Burgers: L = 1, T = 0.5,
+    N_x = 64, N_T = 400 fine steps, 3-level V-cycle with F-relaxation and m = 2
+    (N_t = 400, 200, 100 per level), u0 = (4/3) sin(2 pi x) as exact cell
+    averages; the coarsest level runs at CFL (4/3)(4 dt)/dx = 0.43.  WENO degree
+    k (order s = 2k+1) and the numerical flux (0 LF, 1 Roe) are the
+    experiment's variables."""
+    nx, nt = 64, 400
+    u0 = (4.0 / 3.0) * cell_average_sin(nx, 1, 0.0)
+    dt = 0.5 / nt
+    name = "e4_burgers_s%d_%s" % (2 * k + 1, "roe" if numflux else "lf")
+    return Problem(name, FLUX_BURGERS, k, stepper, nx, nt, dt, 2, 3, 0, u0, max_iter=max_iter,
+                   tol=-1.0, cfl=(4.0 / 3.0) * dt * nx, numflux=numflux)
 
 
 def random_lines(index: int, nlines: int, nx: int, mean: float = 0.5, amp: float = 0.3) -> np.ndarray:
