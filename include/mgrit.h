@@ -61,9 +61,13 @@ enum {
  * The fine propagator Phi (sec 2.1 - 2.2).
  *   flux     0: Burgers f(u) = u^2/2, lambda = u (eq burgers);
  *            1: linear advection f(u) = a u, lambda = a.
- *   k        WENO polynomial degree (sec 2.1.1): 0 = piecewise constant
- *            (u^-_{i+1/2} = u_i, u^+_{i+1/2} = u_{i+1}); 2 = WENO5-JS with the
- *            printed k = 2 tables, stencil r = {i-r, ..., i-r+2}.
+ *   k        WENO polynomial degree (sec 2.1.1), order s = 2k+1: 0 = piecewise
+ *            constant (u^-_{i+1/2} = u_i, u^+_{i+1/2} = u_{i+1}); 1 = WENO3;
+ *            2 = WENO5-JS with the printed k = 2 tables; 3 = WENO7.  Stencil
+ *            r = {i-r, ..., i-r+k}; for k = 1 and 3 the tables of eq C, B and D
+ *            are those their definitions give (the paper prints k = 2 only).
+ *            k = 3 runs on lines of at most 4096 cells (else
+ *            MGRIT_EUNSUPPORTED).
  *   stepper  1: forward Euler (eq SSPRK1); 2: SSPRK2; 3: SSPRK3 (eq SSPRK3).
  *   nx       number of cells N_x >= 8.
  *   a        advection speed (flux == 1).
@@ -79,6 +83,13 @@ enum {
  *            line.  The LF flux is F = (f(u^-)+f(u^+))/2 - alpha (u^+ - u^-)/2
  *            (eq LFflux with the dissipative sign that makes it the
  *            Lax-Friedrichs scheme of eq fineLF).
+ *   numflux  0: Lax-Friedrichs (eq LFflux).  1: Roe with the Harten-Hyman
+ *            entropy fix (sec 2.1.3, eq roeflux):
+ *            F = (f(u^-)+f(u^+))/2 - q_H(lh) (u^+ - u^-)/2 with the Roe speed
+ *            lh = (f(u^+)-f(u^-))/(u^+-u^-) (u_hat = (u^-+u^+)/2 for Burgers,
+ *            a for advection), q_H = (lh^2/delta + delta)/2 when |lh| < delta
+ *            and |lh| otherwise, delta = max(0, lh - lambda(u^-),
+ *            lambda(u^+) - lh).  With 1, alpha_fixed and lf_dx_dt must be 0.
  */
 typedef struct {
     int32_t flux;
@@ -90,7 +101,7 @@ typedef struct {
     double L;
     double alpha_fixed;
     int32_t lf_dx_dt;
-    int32_t pad_;
+    int32_t numflux;
 } mgrit_scheme;
 
 /*
@@ -219,6 +230,24 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
                 void* workspace, size_t ws_bytes, double* res_hist, int32_t* iters, void* stream);
 
 /*
+ * mgrit_cycle_levels -- mgrit_cycle with the scheme schemes[l] on level l
+ * (sec 4, Fig. MGRITweno_diffOrd: the WENO degree k and the Runge-Kutta
+ * scheme may rise or fall across levels; the numerical flux and eps may
+ * change too).  Level l still steps with m^l dt; the FAS restriction from
+ * level l applies Phi_{l+1} with schemes[l+1].
+ *   schemes   HOST array of p->levels schemes with the same nx, L and flux
+ *             (and a, for advection).  Lines of more than 4096 cells need
+ *             the same scheme on every level (else MGRIT_EUNSUPPORTED).
+ *   p         as for mgrit_cycle; coarse_integrator must be 0.
+ *   workspace at least mgrit_workspace_bytes(&schemes[0], p) bytes.
+ * Other arguments, synchronisation and return codes as for mgrit_cycle.
+ * With the same scheme on every level the iterates equal mgrit_cycle's bit
+ * for bit.
+ */
+int mgrit_cycle_levels(const mgrit_scheme* schemes, const mgrit_params* p, const double* u0, double* u,
+                       void* workspace, size_t ws_bytes, double* res_hist, int32_t* iters, void* stream);
+
+/*
  * Discrete adjoint (the derivative of Phi written by hand; not in the paper).
  *
  * mgrit_phi_vjp -- lam_out[b] = (dPhi/du(u[b]))^T lam_in[b] for independent
@@ -228,6 +257,9 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
  * interface/side, interfaces in increasing order, u^- before u^+).  Arrays are
  * nlines x nx.  The line must be a multiple of the cells per thread of the
  * adjoint kernel (any nx <= 512, even nx <= 1024); else MGRIT_EUNSUPPORTED.
+ * The adjoint covers the Lax-Friedrichs flux with k = 0 or 2; other schemes
+ * return MGRIT_EUNSUPPORTED here and in mgrit_adjoint (and 0 from
+ * mgrit_adjoint_workspace_bytes).
  */
 int mgrit_phi_vjp(const mgrit_scheme* s, double dt, const double* u, const double* lam_in, double* lam_out,
                   int64_t nlines, void* stream);

@@ -253,18 +253,34 @@ int check_scheme(const mgrit_scheme* s)
 {
     if (s == nullptr) return fail(MGRIT_EINVAL, "scheme is NULL");
     if (s->flux != 0 && s->flux != 1) return fail(MGRIT_EINVAL, "flux must be 0 (Burgers) or 1 (advection), got %d", s->flux);
-    if (s->k != 0 && s->k != 2) return fail(MGRIT_EINVAL, "k must be 0 or 2, got %d", s->k);
+    if (s->k < 0 || s->k > 3) return fail(MGRIT_EINVAL, "k must be 0, 1, 2 or 3, got %d", s->k);
     if (s->stepper < 1 || s->stepper > 3) return fail(MGRIT_EINVAL, "stepper must be 1, 2 or 3, got %d", s->stepper);
     if (s->nx < 8) return fail(MGRIT_EINVAL, "nx must be >= 8, got %d", s->nx);
     if (!(s->L > 0.0) || !std::isfinite(s->L)) return fail(MGRIT_EINVAL, "L must be positive and finite");
-    if (s->k == 2 && (!(s->eps > 0.0) || !std::isfinite(s->eps))) return fail(MGRIT_EINVAL, "eps must be positive");
+    if (s->k > 0 && (!(s->eps > 0.0) || !std::isfinite(s->eps))) return fail(MGRIT_EINVAL, "eps must be positive");
     if (s->flux == 1 && !std::isfinite(s->a)) return fail(MGRIT_EINVAL, "advection speed must be finite");
     if (!(s->alpha_fixed >= 0.0) || !std::isfinite(s->alpha_fixed)) return fail(MGRIT_EINVAL, "alpha_fixed must be >= 0");
     if (s->lf_dx_dt != 0 && s->lf_dx_dt != 1) return fail(MGRIT_EINVAL, "lf_dx_dt must be 0 or 1");
+    if (s->numflux != 0 && s->numflux != 1) return fail(MGRIT_EINVAL, "numflux must be 0 (LF) or 1 (Roe), got %d", s->numflux);
+    if (s->numflux == 1 && (s->alpha_fixed > 0.0 || s->lf_dx_dt != 0))
+        return fail(MGRIT_EINVAL, "alpha_fixed and lf_dx_dt apply to the Lax-Friedrichs flux only");
     KernelCfg c;
     int tiles = 0;
-    if (!choose_tiled(s->nx, &c, &tiles) && !choose_cfg(s->nx, kLatencyLines, &c))
+    const bool split = choose_tiled(s->nx, &c, &tiles);
+    if (!split && !choose_cfg(s->nx, kLatencyLines, &c))
         return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", s->nx);
+    if (split && s->k == 3)
+        return fail(MGRIT_EUNSUPPORTED, "WENO7 (k = 3) runs on lines of one workgroup (at most %d cells), nx = %d",
+                    kMaxLine, s->nx);
+    return MGRIT_OK;
+}
+
+// the discrete adjoint covers the LF flux with k = 0 or 2
+int check_adjoint_scheme(const mgrit_scheme* s)
+{
+    if ((s->k != 0 && s->k != 2) || s->numflux != 0)
+        return fail(MGRIT_EUNSUPPORTED, "the adjoint covers the Lax-Friedrichs flux with k = 0 or 2 (k = %d, numflux = %d)",
+                    s->k, s->numflux);
     return MGRIT_OK;
 }
 
@@ -288,6 +304,8 @@ mgk::PhiConst phi_const(const mgrit_scheme* s, double dt = 0.0)
     pc.eps = s->eps;
     pc.alpha_fixed = s->alpha_fixed;
     if (s->lf_dx_dt && dt > 0.0) pc.alpha_fixed = (s->L / (double)s->nx) / dt;
+    pc.roe = s->numflux;
+    pc.pad_ = 0;
     return pc;
 }
 
@@ -341,6 +359,9 @@ int launch(int kc, const SweepArgs& a_in, const mgrit_scheme* s, hipStream_t st,
     int tiles = 0;
     SweepArgs a = a0;
     const bool tiled = choose_tiled(s->nx, &cfg, &tiles);
+    if (tiled && s->k == 3) return fail(MGRIT_EUNSUPPORTED, "WENO7 (k = 3) does not run on split lines");
+    if (tiled && (a0.coarse_split || a0.gc_sub != nullptr))
+        return fail(MGRIT_EUNSUPPORTED, "a scheme per level does not run on split lines");
     if (tiled) {
         char* scratch = tl_tile_scratch;
         if (scratch == nullptr) {
@@ -534,8 +555,17 @@ Layout make_layout(const mgrit_scheme* s, const mgrit_params* p)
 // ---------------------------------------------------------------------------
 // the cycle driver
 // ---------------------------------------------------------------------------
+// two schemes that compute the same Phi
+bool same_scheme(const mgrit_scheme* a, const mgrit_scheme* b)
+{
+    return a == b || (a->flux == b->flux && a->k == b->k && a->stepper == b->stepper && a->nx == b->nx &&
+                      a->a == b->a && a->eps == b->eps && a->L == b->L && a->alpha_fixed == b->alpha_fixed &&
+                      a->lf_dx_dt == b->lf_dx_dt && a->numflux == b->numflux);
+}
+
 struct Cycle {
-    const mgrit_scheme* s;
+    const mgrit_scheme* s;        // level 0
+    const mgrit_scheme* sl[16];   // the scheme of level l (sl[l] == s unless a scheme per level is given)
     const mgrit_params* p;
     Layout ly;
     char* ws;
@@ -569,11 +599,16 @@ struct Cycle {
     int64_t cstride(int l) { return l == 0 ? cstride0 : p->m; }
     double* fout(int l) { return (l == 0 && !fstore0) ? nullptr : U(l); }
     int kc(int l, int base0, int basec) { return l == 0 ? base0 : basec; }
+    const mgrit_scheme* S(int l) { return sl[l]; }
+    // the FAS restriction from level l applies Phi_{l+1} inside the level-l
+    // kernel when both levels have the same scheme; otherwise a second launch
+    // with the level-(l+1) scheme subtracts it
+    bool fused_restrict(int l) { return same_scheme(sl[l], sl[l + 1]); }
 
     // F + C-step into the side buffer (first half of FCF); residual at level 0
     int sweep_fc(int l, bool resid)
     {
-        SweepArgs a = base_args(s);
+        SweepArgs a = base_args(S(l));
         psi_args(a, l);
         a.nchunks = ly.N[l] / p->m;
         a.m = p->m;
@@ -589,13 +624,13 @@ struct Cycle {
         a.cref_stride = cstride(l);
         a.resid_partial = resid ? partial() : nullptr;
         a.flag = flag;
-        return launch(kc(l, MGRIT_KC_RELAX_FC, MGRIT_KC_RELAX_FC_C), a, s, st, (double)a.nchunks * p->m);
+        return launch(kc(l, MGRIT_KC_RELAX_FC, MGRIT_KC_RELAX_FC_C), a, S(l), st, (double)a.nchunks * p->m);
     }
 
     // F-relaxation (from the side buffer after a C-relaxation) + FAS restriction to level l+1
     int sweep_fr(int l, bool from_side, bool resid)
     {
-        SweepArgs a = base_args(s);
+        SweepArgs a = base_args(S(l));
         psi_args(a, l);
         a.nchunks = ly.N[l] / p->m;
         a.m = p->m;
@@ -623,13 +658,29 @@ struct Cycle {
         a.gc_out = G(l + 1);
         a.resid_partial = resid ? partial() : nullptr;
         a.flag = flag;
-        return launch(kc(l, MGRIT_KC_RELAX_FR, MGRIT_KC_RELAX_FR_C), a, s, st, (double)a.nchunks * (p->m + 1));
+        const bool fused = fused_restrict(l);
+        a.coarse_split = fused ? 0 : 1;
+        int rc = launch(kc(l, MGRIT_KC_RELAX_FR, MGRIT_KC_RELAX_FR_C), a, S(l), st, (double)a.nchunks * (p->m + 1));
+        if (rc || fused) return rc;
+        // g_c^{i+1} -= Phi_{l+1}(u_l^{mi}) with the level-(l+1) scheme; the chunk
+        // starts are the committed C-points of level l
+        SweepArgs b = base_args(S(l + 1));
+        b.nchunks = ly.N[l] / p->m;
+        b.m = p->m;
+        b.nsteps = 0;
+        b.end_mode = mgk::END_PHI;
+        b.dt = dtl[l + 1];
+        b.ustart = U(l);
+        b.ustart_stride = cstride(l);
+        b.gc_sub = G(l + 1);
+        b.flag = flag;
+        return launch(MGRIT_KC_RELAX_FR_C, b, S(l + 1), st, (double)b.nchunks);
     }
 
     // ideal interpolation: inject level l+1 into the C-points of level l, then F-relax
     int interp(int l, bool relax_f)
     {
-        SweepArgs a = base_args(s);
+        SweepArgs a = base_args(S(l));
         psi_args(a, l);
         a.nchunks = ly.N[l] / p->m;
         a.m = p->m;
@@ -644,13 +695,13 @@ struct Cycle {
         a.fout = relax_f ? fout(l) : nullptr;
         a.g = G(l);
         a.flag = flag;
-        return launch(MGRIT_KC_INTERP, a, s, st, (double)a.nchunks * a.nsteps);
+        return launch(MGRIT_KC_INTERP, a, S(l), st, (double)a.nchunks * a.nsteps);
     }
 
     // serial solve on level l: v^0 = g^0, v^n = Phi(v^{n-1}) + g^n
     int coarse(int l)
     {
-        SweepArgs a = base_args(s);
+        SweepArgs a = base_args(S(l));
         psi_args(a, l);
         a.nchunks = 1;
         a.m = 0;
@@ -664,7 +715,7 @@ struct Cycle {
         a.fout = U(l);
         a.g = G(l);
         a.flag = flag;
-        return launch(MGRIT_KC_COARSE, a, s, st, (double)ly.N[l]);
+        return launch(MGRIT_KC_COARSE, a, S(l), st, (double)ly.N[l]);
     }
 
     int relax(int l)  // F or FCF on level l >= 1, then restriction
@@ -914,6 +965,7 @@ int mgrit_phi_vjp(const mgrit_scheme* s, double dt, const double* u, const doubl
 {
     int rc = check_scheme(s);
     if (rc) return rc;
+    if ((rc = check_adjoint_scheme(s))) return rc;
     {
         KernelCfg c;
         if (!choose_adj_cfg(s->nx, &c))
@@ -959,7 +1011,7 @@ int mgrit_checkpoints(const mgrit_scheme* s, double dt, int32_t nt, int32_t ever
 
 size_t mgrit_adjoint_workspace_bytes(const mgrit_scheme* s, int32_t nt, int32_t every, int32_t parallel_segments)
 {
-    if (check_scheme(s) != MGRIT_OK) return 0;
+    if (check_scheme(s) != MGRIT_OK || check_adjoint_scheme(s) != MGRIT_OK) return 0;
     if (nt < 1 || every < 1 || nt % every != 0 || parallel_segments < 1) {
         fail(MGRIT_EINVAL, "nt must be a positive multiple of every, parallel_segments >= 1");
         return 0;
@@ -980,6 +1032,7 @@ int mgrit_adjoint(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, i
 {
     int rc = check_scheme(s);
     if (rc) return rc;
+    if ((rc = check_adjoint_scheme(s))) return rc;
     if ((rc = check_dt(dt))) return rc;
     const size_t need = mgrit_adjoint_workspace_bytes(s, nt, every, parallel_segments);
     if (need == 0) return MGRIT_EINVAL;
@@ -1083,17 +1136,19 @@ size_t mgrit_workspace_bytes(const mgrit_scheme* s, const mgrit_params* p)
     return make_layout(s, p).total;
 }
 
-int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, double* u, void* workspace,
-                size_t ws_bytes, double* res_hist, int32_t* iters, void* stream)
+// the solve of mgrit_cycle and mgrit_cycle_levels (arguments validated):
+// sl[l] is the scheme of level l
+static int run_cycle(const mgrit_scheme* const* sl, const mgrit_params* p, const double* u0, double* u,
+                     void* workspace, size_t ws_bytes, double* res_hist, int32_t* iters, void* stream)
 {
-    int rc = check_scheme(s);
-    if (rc) return rc;
-    if ((rc = check_params(s, p))) return rc;
+    const mgrit_scheme* s = sl[0];
+    int rc = MGRIT_OK;
     if (u0 == nullptr || u == nullptr || workspace == nullptr) return fail(MGRIT_EINVAL, "NULL array");
     if (res_hist == nullptr || iters == nullptr) return fail(MGRIT_EINVAL, "NULL host output");
     if (((uintptr_t)workspace & 255) != 0) return fail(MGRIT_EINVAL, "workspace must be 256-byte aligned");
     Cycle cy;
     cy.s = s;
+    for (int l = 0; l < 16; ++l) cy.sl[l] = sl[l];
     cy.p = p;
     cy.ly = make_layout(s, p);
     if (ws_bytes < cy.ly.total)
@@ -1207,6 +1262,44 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
     return host_flag ? MGRIT_OK : MGRIT_NOT_CONVERGED;
 }
 
+int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, double* u, void* workspace,
+                size_t ws_bytes, double* res_hist, int32_t* iters, void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if ((rc = check_params(s, p))) return rc;
+    const mgrit_scheme* sl[16];
+    for (int l = 0; l < 16; ++l) sl[l] = s;
+    return run_cycle(sl, p, u0, u, workspace, ws_bytes, res_hist, iters, stream);
+}
+
+int mgrit_cycle_levels(const mgrit_scheme* schemes, const mgrit_params* p, const double* u0, double* u,
+                       void* workspace, size_t ws_bytes, double* res_hist, int32_t* iters, void* stream)
+{
+    if (schemes == nullptr) return fail(MGRIT_EINVAL, "schemes is NULL");
+    int rc = check_scheme(&schemes[0]);
+    if (rc) return rc;
+    if ((rc = check_params(&schemes[0], p))) return rc;
+    if (p->coarse_integrator != 0)
+        return fail(MGRIT_EINVAL, "coarse_integrator replaces the coarse schemes: use mgrit_cycle");
+    const mgrit_scheme* s0 = &schemes[0];
+    bool mixed = false;
+    for (int l = 1; l < p->levels; ++l) {
+        const mgrit_scheme* sl = &schemes[l];
+        if ((rc = check_scheme(sl))) return rc;
+        if (sl->nx != s0->nx || sl->L != s0->L || sl->flux != s0->flux || (s0->flux == 1 && sl->a != s0->a))
+            return fail(MGRIT_EINVAL, "level %d: every level must have the same nx, L and conservation law", l);
+        if (!same_scheme(&schemes[l - 1], sl)) mixed = true;
+    }
+    KernelCfg c;
+    int tiles = 0;
+    if (mixed && choose_tiled(s0->nx, &c, &tiles))
+        return fail(MGRIT_EUNSUPPORTED, "a scheme per level runs on lines of one workgroup (at most %d cells)", kMaxLine);
+    const mgrit_scheme* sl[16];
+    for (int l = 0; l < 16; ++l) sl[l] = &schemes[l < p->levels ? l : p->levels - 1];
+    return run_cycle(sl, p, u0, u, workspace, ws_bytes, res_hist, iters, stream);
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -1304,6 +1397,7 @@ int plan_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p,
         const mgrit_params pp = problem_params(p, &q);
         Cycle cy;
         cy.s = &q.scheme;
+        for (int l = 0; l < 16; ++l) cy.sl[l] = &q.scheme;
         cy.p = &pp;
         cy.ly = bp->ly[i];
         cy.ws = (ws != nullptr ? ws : (char*)nullptr) + bp->ly_off[i];

@@ -26,17 +26,24 @@ hipError_t launch_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int ste
     return launch_adjoint_ks<2, 3>(a, cfg, store_mode, s);
 }
 
+// (k, stepper) -> the instantiation compiled in sweep_k<k>_s<stepper>.hip
+#define MGK_DISPATCH_KS(FN, K, ...)                                   \
+    do {                                                              \
+        if (stepper == 1) return FN<K, 1>(__VA_ARGS__);               \
+        if (stepper == 2) return FN<K, 2>(__VA_ARGS__);               \
+        return FN<K, 3>(__VA_ARGS__);                                 \
+    } while (0)
+
 hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
 {
     if (a.nchunks <= 0) return hipSuccess;
-    if (k == 0) {
-        if (stepper == 1) return launch_sweep_ks<0, 1>(a, cfg, s);
-        if (stepper == 2) return launch_sweep_ks<0, 2>(a, cfg, s);
-        return launch_sweep_ks<0, 3>(a, cfg, s);
+    switch (k) {
+    case 0: MGK_DISPATCH_KS(launch_sweep_ks, 0, a, cfg, s);
+    case 1: MGK_DISPATCH_KS(launch_sweep_ks, 1, a, cfg, s);
+    case 2: MGK_DISPATCH_KS(launch_sweep_ks, 2, a, cfg, s);
+    case 3: MGK_DISPATCH_KS(launch_sweep_ks, 3, a, cfg, s);
+    default: return hipErrorInvalidValue;
     }
-    if (stepper == 1) return launch_sweep_ks<2, 1>(a, cfg, s);
-    if (stepper == 2) return launch_sweep_ks<2, 2>(a, cfg, s);
-    return launch_sweep_ks<2, 3>(a, cfg, s);
 }
 
 template <int K, int ST>
@@ -59,17 +66,16 @@ hipError_t launch_tiled_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, i
     return launch_tiled_adjoint_ks<2, 3>(a, cfg, store_mode, s);
 }
 
+// split lines keep three ghost cells per side: WENO degree 0, 1 or 2
 hipError_t launch_tiled(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
 {
     if (a.nchunks <= 0) return hipSuccess;
-    if (k == 0) {
-        if (stepper == 1) return launch_tiled_ks<0, 1>(a, cfg, s);
-        if (stepper == 2) return launch_tiled_ks<0, 2>(a, cfg, s);
-        return launch_tiled_ks<0, 3>(a, cfg, s);
+    switch (k) {
+    case 0: MGK_DISPATCH_KS(launch_tiled_ks, 0, a, cfg, s);
+    case 1: MGK_DISPATCH_KS(launch_tiled_ks, 1, a, cfg, s);
+    case 2: MGK_DISPATCH_KS(launch_tiled_ks, 2, a, cfg, s);
+    default: return hipErrorInvalidValue;
     }
-    if (stepper == 1) return launch_tiled_ks<2, 1>(a, cfg, s);
-    if (stepper == 2) return launch_tiled_ks<2, 2>(a, cfg, s);
-    return launch_tiled_ks<2, 3>(a, cfg, s);
 }
 
 // dst[b] = src for b < nlines (fill every node with the initial condition)
@@ -163,14 +169,13 @@ hipError_t launch_batch_ks(const BatchLaunch& t, const KernelCfg& cfg, hipStream
 hipError_t launch_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
 {
     if (t.nblocks <= 0) return hipSuccess;
-    if (k == 0) {
-        if (stepper == 1) return launch_batch_ks<0, 1>(t, cfg, s);
-        if (stepper == 2) return launch_batch_ks<0, 2>(t, cfg, s);
-        return launch_batch_ks<0, 3>(t, cfg, s);
+    switch (k) {
+    case 0: MGK_DISPATCH_KS(launch_batch_ks, 0, t, cfg, s);
+    case 1: MGK_DISPATCH_KS(launch_batch_ks, 1, t, cfg, s);
+    case 2: MGK_DISPATCH_KS(launch_batch_ks, 2, t, cfg, s);
+    case 3: MGK_DISPATCH_KS(launch_batch_ks, 3, t, cfg, s);
+    default: return hipErrorInvalidValue;
     }
-    if (stepper == 1) return launch_batch_ks<2, 1>(t, cfg, s);
-    if (stepper == 2) return launch_batch_ks<2, 2>(t, cfg, s);
-    return launch_batch_ks<2, 3>(t, cfg, s);
 }
 
 hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s)

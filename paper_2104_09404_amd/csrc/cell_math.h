@@ -1,6 +1,7 @@
-// cell_math.h -- per-cell arithmetic of the sweep kernels (WENO5 reconstruction
-// and Lax-Friedrichs flux), written once and compiled for the GPU by the
-// kernels and for the host by the CPU test of the kernel arithmetic.
+// cell_math.h -- per-cell arithmetic of the sweep kernels (WENO reconstructions
+// of orders 3, 5 and 7, Lax-Friedrichs and Roe fluxes), written once and
+// compiled for the GPU by the kernels and for the host by the CPU test of the
+// kernel arithmetic.
 #pragma once
 #include <math.h>
 
@@ -81,6 +82,91 @@ MGK_HD void weno5_cell(double w0, double w1, double w2, double w3, double w4, do
     const double dm = fma(0.1, PCR, fma(0.6, PLR, 0.3 * PLC));
     const double np = fma(PCR, dL, fma(PLR, dC, PLC * dR));
     const double dp = fma(0.3, PCR, fma(0.6, PLR, 0.1 * PLC));
+    const double inv = recip(dm * dp);
+    um = nm * (dp * inv);
+    up = np * (dm * inv);
+}
+
+// WENO3 (k = 1) reconstructions of cell p from w0, w1, w2 = u_{p-1}, u_p, u_{p+1}
+// (sec 2.1.1 with two 2-cell stencils):
+//   u^-_{p+1/2}: (w1 + w2)/2 with weight 2/3 and indicator (w2 - w1)^2,
+//                (3 w1 - w0)/2 with weight 1/3 and indicator (w1 - w0)^2;
+//   u^+_{p-1/2}: the mirror image, (w0 + w1)/2 (2/3, (w1 - w0)^2) and
+//                (3 w1 - w2)/2 (1/3, (w2 - w1)^2).
+// With s = (eps + beta)^2 the weights reduce to u^- = (2 sL cR + sR cL)/(2 sL + sR)
+// (sR of the right stencil, sL of the left one) and u^+ likewise; both faces
+// share one reciprocal.
+MGK_HD void weno3_cell(double w0, double w1, double w2, double eps, double& um, double& up)
+{
+    const double dl = w1 - w0, dr = w2 - w1;
+    double sL = fma(dl, dl, eps), sR = fma(dr, dr, eps);
+    sL *= sL;
+    sR *= sR;
+    const double cR = 0.5 * (w1 + w2), cL = fma(1.5, w1, -0.5 * w0);
+    const double pL = 0.5 * (w0 + w1), pR = fma(1.5, w1, -0.5 * w2);
+    const double nm = fma(2.0 * sL, cR, sR * cL), dm = fma(2.0, sL, sR);
+    const double np = fma(2.0 * sR, pL, sL * pR), dp = fma(2.0, sR, sL);
+    const double inv = recip(dm * dp);
+    um = nm * (dp * inv);
+    up = np * (dm * inv);
+}
+
+// WENO7 (k = 3) reconstructions of cell p from w0..w6 = u_{p-3}..u_{p+3}
+// (sec 2.1.1 with four 4-cell stencils; stencil r = cells p-r..p-r+3).
+// Candidates of u^-_{p+1/2} (times 12) and linear weights (times 35):
+//   r = 0 (w3..w6):  3 w3 + 13 w4 -  5 w5 +  1 w6      4
+//   r = 1 (w2..w5): -1 w2 +  7 w3 +  7 w4 -  1 w5     18
+//   r = 2 (w1..w4):  1 w1 -  5 w2 + 13 w3 +  3 w4     12
+//   r = 3 (w0..w3): -3 w0 + 13 w1 - 23 w2 + 25 w3      1
+// Indicators (times 240) of the stencils on cells a, b, c, d (left to right):
+//   r = 3: a(547a - 3882b + 4642c - 1854d) + b(7043b - 17246c + 7042d) + c(11003c - 9402d) + 2107d^2
+//   r = 2: a(267a - 1642b + 1602c - 494d) + b(2843b - 5966c + 1922d) + c(3443c - 2522d) + 547d^2
+//   r = 1: a(547a - 2522b + 1922c - 494d) + b(3443b - 5966c + 1602d) + c(2843c - 1642d) + 267d^2
+//   r = 0: a(2107a - 9402b + 7042c - 1854d) + b(11003b - 17246c + 4642d) + c(7043c - 3882d) + 547d^2
+// u^+_{p-1/2} is the mirror image: its stencil r covers the cells of u^-'s
+// stencil 3-r (same indicator) with the candidate coefficients reversed.
+// With s_r = (eps + beta_r)^2 the weights d_r/s_r are scaled by s0 s1 s2 s3, so
+// each face needs products of three s and both share one reciprocal.
+MGK_HD void weno7_cell(double w0, double w1, double w2, double w3, double w4, double w5, double w6, double eps,
+                       double& um, double& up)
+{
+    const double i240 = 1.0 / 240.0;
+    double b3 = w0 * (547.0 * w0 - 3882.0 * w1 + 4642.0 * w2 - 1854.0 * w3) +
+                w1 * (7043.0 * w1 - 17246.0 * w2 + 7042.0 * w3) + w2 * (11003.0 * w2 - 9402.0 * w3) +
+                2107.0 * w3 * w3;
+    double b2 = w1 * (267.0 * w1 - 1642.0 * w2 + 1602.0 * w3 - 494.0 * w4) +
+                w2 * (2843.0 * w2 - 5966.0 * w3 + 1922.0 * w4) + w3 * (3443.0 * w3 - 2522.0 * w4) +
+                547.0 * w4 * w4;
+    double b1 = w2 * (547.0 * w2 - 2522.0 * w3 + 1922.0 * w4 - 494.0 * w5) +
+                w3 * (3443.0 * w3 - 5966.0 * w4 + 1602.0 * w5) + w4 * (2843.0 * w4 - 1642.0 * w5) +
+                267.0 * w5 * w5;
+    double b0 = w3 * (2107.0 * w3 - 9402.0 * w4 + 7042.0 * w5 - 1854.0 * w6) +
+                w4 * (11003.0 * w4 - 17246.0 * w5 + 4642.0 * w6) + w5 * (7043.0 * w5 - 3882.0 * w6) +
+                547.0 * w6 * w6;
+    double s0 = fma(b0, i240, eps), s1 = fma(b1, i240, eps), s2 = fma(b2, i240, eps), s3 = fma(b3, i240, eps);
+    s0 *= s0;
+    s1 *= s1;
+    s2 *= s2;
+    s3 *= s3;
+    const double s01 = s0 * s1, s23 = s2 * s3;
+    const double P0 = s1 * s23, P1 = s0 * s23, P2 = s01 * s3, P3 = s01 * s2;  // prod of the other three
+    const double i12 = 1.0 / 12.0;
+    // u^-: candidate r with weight d_r on P_r
+    const double c0 = (3.0 * w3 + 13.0 * w4 - 5.0 * w5 + w6) * i12;
+    const double c1 = (-w2 + 7.0 * w3 + 7.0 * w4 - w5) * i12;
+    const double c2 = (w1 - 5.0 * w2 + 13.0 * w3 + 3.0 * w4) * i12;
+    const double c3 = (-3.0 * w0 + 13.0 * w1 - 23.0 * w2 + 25.0 * w3) * i12;
+    // u^+: mirror stencil r covers u^-'s stencil 3-r, weight d_r on P_{3-r}
+    const double e0 = (3.0 * w3 + 13.0 * w2 - 5.0 * w1 + w0) * i12;
+    const double e1 = (-w4 + 7.0 * w3 + 7.0 * w2 - w1) * i12;
+    const double e2 = (w5 - 5.0 * w4 + 13.0 * w3 + 3.0 * w2) * i12;
+    const double e3 = (-3.0 * w6 + 13.0 * w5 - 23.0 * w4 + 25.0 * w3) * i12;
+    const double q0 = 4.0 * P0, q1 = 18.0 * P1, q2 = 12.0 * P2, q3 = P3;
+    const double r0 = 4.0 * P3, r1 = 18.0 * P2, r2 = 12.0 * P1, r3 = P0;
+    const double nm = fma(q0, c0, fma(q1, c1, fma(q2, c2, q3 * c3)));
+    const double dm = (q0 + q1) + (q2 + q3);
+    const double np = fma(r0, e0, fma(r1, e1, fma(r2, e2, r3 * e3)));
+    const double dp = (r0 + r1) + (r2 + r3);
     const double inv = recip(dm * dp);
     um = nm * (dp * inv);
     up = np * (dm * inv);
@@ -170,6 +256,23 @@ MGK_HD double flux_f(double u, double fa, double fb) { return u * fma(fa, u, fb)
 MGK_HD double lf_flux2(double uL, double uR, double fa, double fb, double alpha)
 {
     return fma(-alpha, uR - uL, flux_f(uL, fa, fb) + flux_f(uR, fa, fb));
+}
+
+// Twice the Roe flux with the Harten-Hyman entropy fix (sec 2.1.3, eq roeflux,
+// with the 1/2 on the dissipation and q_H = (lh^2/delta + delta)/2 inside the
+// fix) for f(u) = u (fa u + fb):
+//   lambda(u) = 2 fa u + fb, Roe speed lh = (f(uR) - f(uL))/(uR - uL) = fa (uL + uR) + fb
+//   (for Burgers the eigenvalue at the average (uL + uR)/2; for advection a),
+//   delta = max(0, lh - lambda(uL), lambda(uR) - lh),
+//   2F = f(uL) + f(uR) - q_H(lh) (uR - uL).
+MGK_HD double roe_flux2(double uL, double uR, double fa, double fb)
+{
+    const double lh = fma(fa, uL + uR, fb);
+    const double lL = fma(2.0 * fa, uL, fb), lR = fma(2.0 * fa, uR, fb);
+    const double delta = fmax(0.0, fmax(lh - lL, lR - lh));
+    const double alh = fabs(lh);
+    const double q = (alh < delta) ? 0.5 * (lh * lh / delta + delta) : alh;
+    return fma(-q, uR - uL, flux_f(uL, fa, fb) + flux_f(uR, fa, fb));
 }
 
 // alpha_LF = max |lambda(u^{+-})| from m = max |u^{+-}|: with lambda = 2 fa u + fb

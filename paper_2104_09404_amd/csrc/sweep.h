@@ -10,9 +10,11 @@ namespace mgk {
 // (Burgers: fa = 1/2, fb = 0; linear advection: fa = 0, fb = a).
 struct PhiConst {
     double fa, fb;
-    double half_inv_dx;  // 1/(2 dx): the flux difference uses twice the LF flux
+    double half_inv_dx;  // 1/(2 dx): the flux difference uses twice the flux
     double eps;
     double alpha_fixed;  // > 0 replaces the global alpha_LF
+    int roe;             // 1: Roe flux with the Harten-Hyman fix instead of LF
+    int pad_;
 };
 
 enum EndMode : int {
@@ -36,7 +38,8 @@ struct SweepArgs {
     int end_mode;
     int inject_last;       // chunk nchunks-1 also copies ustart[nchunks] -> ucommit[nchunks]
     int coarse_injection;  // END_RESTRICT: coarse guess by injection instead of eq restriction::u
-    int pad_;
+    int coarse_split;      // END_RESTRICT: store g_c = t only; Phi_{l+1} of the chunk start is
+                           // subtracted by a separate END_PHI launch (gc_sub) with the scheme of level l+1
     double dt;
     double dt_next;        // step of the next-coarser level (END_RESTRICT)
     PhiConst pc;
@@ -57,6 +60,7 @@ struct SweepArgs {
     double* resid_partial;  // per-chunk sum of squared C-point residuals (nullable)
     double* uc_out;
     double* gc_out;
+    double* gc_sub;         // END_PHI: gc_sub[(c+1)*nx ..] -= Phi(x) instead of storing at side_out[c]
     const int* flag;        // if non-null and *flag != 0 the launch does nothing
     // fine-integrator matching (first order, forward Euler kernels only): the
     // steps of this launch apply Psi of order psi_order - 1 matching psi_M fine

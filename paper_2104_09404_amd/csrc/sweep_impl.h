@@ -144,11 +144,45 @@ struct Smem {
     }
 };
 
-// A(V) for the thread's cells: eq spaceDisc with the LF flux (eq LFflux) and
-// either the trivial (K = 0) or the WENO5 (K = 2) reconstruction.
+// WENO reconstructions of the thread's cells from its window w[p] = cell
+// j0 - 3 + p (p = 0..CPT+5): um[q] = u^-_{j+1/2}, up[q] = u^+_{j-1/2} of cell
+// j = j0 + q, for degree K = 0 (piecewise constant), 1, 2 or 3 (s = 1, 3, 5, 7).
+template <int CPT, int K>
+__device__ __forceinline__ void reconstruct(const double (&w)[CPT + 6], double eps, double (&um)[CPT],
+                                            double (&up)[CPT])
+{
+    if constexpr (K == 0) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            um[q] = w[3 + q];
+            up[q] = w[3 + q];
+        }
+    } else if constexpr (K == 1) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) weno3_cell(w[q + 2], w[q + 3], w[q + 4], eps, um[q], up[q]);
+    } else if constexpr (K == 2) {
+        double E[CPT + 6];
+#pragma unroll
+        for (int p = 2; p <= CPT + 3; ++p) E[p] = weno5_e(w[p - 1], w[p], w[p + 1], eps);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int p = q + 3;
+            weno5_cell(w[p - 2], w[p - 1], w[p], w[p + 1], w[p + 2], E[p - 1], E[p], E[p + 1], um[q], up[q]);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+            weno7_cell(w[q], w[q + 1], w[q + 2], w[q + 3], w[q + 4], w[q + 5], w[q + 6], eps, um[q], up[q]);
+    }
+}
+
+// A(V) for the thread's cells: eq spaceDisc with the LF flux (eq LFflux) or,
+// when pc.roe is set, the Roe flux with the Harten-Hyman fix (eq roeflux),
+// and a WENO reconstruction of degree K.
 // RAG: the line length is not a multiple of CPT, so one thread is ragged.
 // par selects the alpha_LF slots of this stage (the other half is still read
-// by slow waves of the previous stage until the first barrier).
+// by slow waves of the previous stage until the first barrier).  The Roe flux
+// is local to its interface: no reduction, pc.roe is uniform over the launch.
 template <int CPT, int NW, int K, bool RAG>
 __device__ __forceinline__ void op_A(const double (&V)[CPT], double (&A)[CPT], const Geo<CPT, NW>& g,
                                      const Smem<CPT, NW>& sm, const PhiConst& pc, int& par)
@@ -167,31 +201,15 @@ __device__ __forceinline__ void op_A(const double (&V)[CPT], double (&A)[CPT], c
         for (int q = 0; q < CPT; ++q)
             if (q >= g.nvalid) w[3 + q] = sm.line[g.slot(wrapi(g.j0 + q, g.nx))];
     }
-    double um[CPT], up[CPT];
-    if (K == 0) {
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            um[q] = w[3 + q];
-            up[q] = w[3 + q];
-        }
-    } else {
+    if constexpr (K > 0) {
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
             w[p] = sm.line[g.halo[p]];
             w[CPT + 3 + p] = sm.line[g.halo[3 + p]];
         }
-        double E[CPT + 6];
-#pragma unroll
-        for (int p = 2; p <= CPT + 3; ++p) E[p] = weno5_e(w[p - 1], w[p], w[p + 1], pc.eps);
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const int p = q + 3;
-            weno5_cell(w[p - 2], w[p - 1], w[p], w[p + 1], w[p + 2], E[p - 1], E[p], E[p + 1], um[q], up[q]);
-        }
     }
-    double lmax = 0.0;
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) lmax = fmax(lmax, fmax(fabs(um[q]), fabs(up[q])));
+    double um[CPT], up[CPT];
+    reconstruct<CPT, K>(w, pc.eps, um, up);
     double last = um[CPT - 1];
     if (RAG && g.ragged) {
 #pragma unroll
@@ -200,30 +218,45 @@ __device__ __forceinline__ void op_A(const double (&V)[CPT], double (&A)[CPT], c
     }
     sm.bm[g.t] = last;
     sm.bp[g.t] = up[0];
-    // alpha_LF: max|u^{+-}| over the line (exact, order independent): wave max,
-    // then one slot per wave (double-buffered by stage parity)
-    if (!g.active) lmax = 0.0;
-    lmax = wave_max(lmax);
-    if (NW > 1 && (threadIdx.x & 63) == 0) sm.amax[par * NW + (threadIdx.x >> 6)] = lmax;
-    __syncthreads();
-
-    double alpha = pc.alpha_fixed;
-    if (!(alpha > 0.0)) {
-        if (NW > 1) {
-#pragma unroll
-            for (int w2 = 0; w2 < NW; ++w2) lmax = fmax(lmax, sm.amax[par * NW + w2]);
-        }
-        alpha = lf_alpha(lmax, pc.fa, pc.fb);
-    }
-    par ^= 1;
-    const double uml = sm.bm[g.left];
-    const double upr = sm.bp[g.right];
     double F[CPT + 1];
+    if (pc.roe) {
+        __syncthreads();
+        const double uml = sm.bm[g.left];
+        const double upr = sm.bp[g.right];
 #pragma unroll
-    for (int q = 0; q <= CPT; ++q) {
-        const double uL = (q == 0) ? uml : um[q - 1];
-        const double uR = (q == CPT) ? upr : up[q];
-        F[q] = lf_flux2(uL, uR, pc.fa, pc.fb, alpha);
+        for (int q = 0; q <= CPT; ++q) {
+            const double uL = (q == 0) ? uml : um[q - 1];
+            const double uR = (q == CPT) ? upr : up[q];
+            F[q] = roe_flux2(uL, uR, pc.fa, pc.fb);
+        }
+    } else {
+        double lmax = 0.0;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) lmax = fmax(lmax, fmax(fabs(um[q]), fabs(up[q])));
+        // alpha_LF: max|u^{+-}| over the line (exact, order independent): wave max,
+        // then one slot per wave (double-buffered by stage parity)
+        if (!g.active) lmax = 0.0;
+        lmax = wave_max(lmax);
+        if (NW > 1 && (threadIdx.x & 63) == 0) sm.amax[par * NW + (threadIdx.x >> 6)] = lmax;
+        __syncthreads();
+
+        double alpha = pc.alpha_fixed;
+        if (!(alpha > 0.0)) {
+            if (NW > 1) {
+#pragma unroll
+                for (int w2 = 0; w2 < NW; ++w2) lmax = fmax(lmax, sm.amax[par * NW + w2]);
+            }
+            alpha = lf_alpha(lmax, pc.fa, pc.fb);
+        }
+        par ^= 1;
+        const double uml = sm.bm[g.left];
+        const double upr = sm.bp[g.right];
+#pragma unroll
+        for (int q = 0; q <= CPT; ++q) {
+            const double uL = (q == 0) ? uml : um[q - 1];
+            const double uR = (q == CPT) ? upr : up[q];
+            F[q] = lf_flux2(uL, uR, pc.fa, pc.fb, alpha);
+        }
     }
 #pragma unroll
     for (int q = 0; q < CPT; ++q) A[q] = (F[q] - F[q + 1]) * pc.half_inv_dx;
@@ -465,6 +498,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
     if constexpr (END == END_NONE) return;
     if constexpr (END == END_PHI) {
         level_step<CPT, NW, K, ST, RAG>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
+        if (a.gc_sub != nullptr) {
+            // the second half of a split FAS restriction: g_c = t - Phi_{l+1}(chunk start)
+            double* out = a.gc_sub + (int64_t)(c + 1) * nx;
+            if (g.active) {
+#pragma unroll
+                for (int q = 0; q < CPT; ++q)
+                    if (q < g.nvalid) out[g.j0 + q] = out[g.j0 + q] - x[q];
+            }
+            return;
+        }
         store_line(x, a.side_out + (int64_t)c * nx, g);
         return;
     }
@@ -490,6 +533,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
     // END_RESTRICT: t = x; coarse guess and FAS right-hand side
     if (a.coarse_injection) copy_line(cnext, a.uc_out + (int64_t)(c + 1) * nx, g);
     else store_line(x, a.uc_out + (int64_t)(c + 1) * nx, g);
+    if (a.coarse_split) {
+        store_line(x, a.gc_out + (int64_t)(c + 1) * nx, g);
+        return;
+    }
     double y[CPT];
     load_line(y, cstart, g);
     PhiConst pcn = a.pc;

@@ -1,0 +1,7 @@
+// Sweep kernels for reconstruction degree k = 3 and SSPRK3 (one translation
+// unit per scheme so that the kernels compile in parallel).
+#include "sweep_impl.h"
+
+namespace mgk {
+template hipError_t launch_sweep_ks<3, 3>(const SweepArgs& a, const KernelCfg& cfg, hipStream_t s);
+}  // namespace mgk

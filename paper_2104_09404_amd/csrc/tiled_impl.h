@@ -11,7 +11,8 @@
 //      interface flux of its cells itself;
 //   3. splits twice the LF flux of each interface (eq LFflux) into the parts
 //      before and after the global coefficient is known,
-//          2F = Fa - alpha_LF Fb,  Fa = f(u^-) + f(u^+),  Fb = u^+ - u^-,
+//          2F = Fa - alpha_LF Fb,  Fa = f(u^-) + f(u^+),  Fb = u^+ - u^-
+//      (with the Roe flux, eq roeflux, Fa is twice the flux and Fb = 0),
 //      and publishes its local max |u^{+-}| and (Fa, Fb) of the three
 //      interfaces inside each edge to a global slot;
 //   4. meets the other tiles of the line at a global counter (one arrival per
@@ -175,7 +176,8 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
     double um[CPT], up[CPT];
     double um_l = 0.0, up_r = 0.0;  // u^- in ghost cell -1, u^+ in ghost cell Tv
     const int pr = 3 + (RAG ? g.nvalid : CPT);  // window position of ghost cell Tv (last thread)
-    if (K == 0) {
+    static_assert(K <= 2, "split lines keep three ghost cells per side: WENO degree <= 2");
+    if constexpr (K == 0) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
             um[q] = w[3 + q];
@@ -186,6 +188,23 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
 #pragma unroll
             for (int p = 3; p <= CPT + 3; ++p)
                 if (p == pr) up_r = w[p];
+        }
+    } else if constexpr (K == 1) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) weno3_cell(w[q + 2], w[q + 3], w[q + 4], pc.eps, um[q], up[q]);
+        if (g.t == 0) {
+            double unused;
+            weno3_cell(w[1], w[2], w[3], pc.eps, um_l, unused);
+        }
+        if (g.t == g.tlast) {
+            if (!RAG || pr == CPT + 3) {
+                double unused;
+                weno3_cell(w[CPT + 2], w[CPT + 3], w[CPT + 4], pc.eps, unused, up_r);
+            } else {
+#pragma unroll
+                for (int q = 0; q < CPT; ++q)
+                    if (q + 3 == pr) up_r = up[q];
+            }
         }
     } else {
         double E[CPT + 6];
@@ -240,8 +259,14 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
         const double uL = (q == 0) ? uml : um[q - 1];
         double uR = (q == CPT) ? upr : up[q];
         if (RAG && q == g.nvalid) uR = upr;
-        Fa[q] = flux_f(uL, pc.fa, pc.fb) + flux_f(uR, pc.fa, pc.fb);
-        Fb[q] = uR - uL;
+        if (pc.roe) {
+            // the Roe flux needs no global coefficient: all of it in Fa
+            Fa[q] = roe_flux2(uL, uR, pc.fa, pc.fb);
+            Fb[q] = 0.0;
+        } else {
+            Fa[q] = flux_f(uL, pc.fa, pc.fb) + flux_f(uR, pc.fa, pc.fb);
+            Fb[q] = uR - uL;
+        }
     }
 
     // stage the edge data in LDS: right faces of cells 0..2, left faces of
@@ -323,7 +348,8 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
             const int idx = (lane < 6) ? 7 + lane : 1 + (lane - 6);
             sm.misc[5 + lane] = load_agent(ts.slot(nb, parity) + idx);
         }
-        if (lane == 0) sm.misc[0] = (pc.alpha_fixed > 0.0) ? pc.alpha_fixed : lf_alpha(mx, pc.fa, pc.fb);
+        if (lane == 0)
+            sm.misc[0] = pc.roe ? 0.0 : (pc.alpha_fixed > 0.0) ? pc.alpha_fixed : lf_alpha(mx, pc.fa, pc.fb);
     }
     __syncthreads();
 

@@ -1,0 +1,8 @@
+// Tiled-line sweep kernels for reconstruction degree k = 1 and the
+// 1-stage Runge-Kutta scheme (one translation unit per scheme so that the
+// kernels compile in parallel).
+#include "tiled_impl.h"
+
+namespace mgk {
+template hipError_t launch_tiled_ks<1, 1>(const SweepArgs& a, const KernelCfg& cfg, hipStream_t s);
+}  // namespace mgk

@@ -27,7 +27,7 @@ EXPORTED = ["mgrit_phi", "mgrit_serial", "mgrit_relax", "mgrit_residual", "mgrit
             "mgrit_cycle", "mgrit_last_error", "mgrit_set_profiling", "mgrit_get_profile",
             "mgrit_kernel_config", "mgrit_set_kernel_config", "mgrit_phi_vjp", "mgrit_checkpoints",
             "mgrit_adjoint_workspace_bytes", "mgrit_adjoint", "mgrit_tiled_config", "mgrit_set_tiled_config",
-            "mgrit_batched_workspace_bytes", "mgrit_cycle_batched"]
+            "mgrit_batched_workspace_bytes", "mgrit_cycle_batched", "mgrit_cycle_levels"]
 
 
 class MgritError(RuntimeError):
@@ -49,7 +49,7 @@ class Scheme(C.Structure):
         ("L", C.c_double),
         ("alpha_fixed", C.c_double),
         ("lf_dx_dt", C.c_int32),
-        ("pad_", C.c_int32),
+        ("numflux", C.c_int32),
     ]
 
 
@@ -117,6 +117,8 @@ def load(path: str = LIB_PATH):
     L.mgrit_workspace_bytes.argtypes = [S, P]
     L.mgrit_workspace_bytes.restype = C.c_size_t
     L.mgrit_cycle.argtypes = [S, P, dp, dp, vp, C.c_size_t, C.POINTER(C.c_double), C.POINTER(C.c_int32), vp]
+    L.mgrit_cycle_levels.argtypes = [S, P, dp, dp, vp, C.c_size_t, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                     vp]
     L.mgrit_last_error.restype = C.c_char_p
     L.mgrit_set_profiling.argtypes = [C.c_int]
     L.mgrit_get_profile.argtypes = [C.POINTER(ProfileEntry), C.c_int]
@@ -167,9 +169,11 @@ def _stream(stream=None) -> Optional[int]:
 
 
 def scheme(nx: int, flux: int = 0, k: int = 2, stepper: int = 3, a: float = 1.0, eps: float = 1e-6,
-           L: float = 1.0, alpha_fixed: float = 0.0, lf_dx_dt: int = 0) -> Scheme:
+           L: float = 1.0, alpha_fixed: float = 0.0, lf_dx_dt: int = 0, numflux: int = 0) -> Scheme:
+    """k: WENO degree (order 2k+1, 0..3); numflux 0 Lax-Friedrichs, 1 Roe with
+    the Harten-Hyman fix."""
     return Scheme(flux=flux, k=k, stepper=stepper, nx=nx, a=a, eps=eps, L=L, alpha_fixed=alpha_fixed,
-                  lf_dx_dt=lf_dx_dt, pad_=0)
+                  lf_dx_dt=lf_dx_dt, numflux=numflux)
 
 
 def fine_lf_scheme(nx: int, flux: int = 0, a: float = 1.0, L: float = 1.0) -> Scheme:
@@ -188,7 +192,8 @@ def params(nt: int, dt: float, m: int, levels: int, relax: int = 1, cycle: int =
 
 
 def scheme_from_problem(pb) -> Scheme:
-    return scheme(pb.nx, flux=pb.flux, k=pb.k, stepper=pb.stepper, a=pb.a, eps=pb.eps, L=pb.L)
+    return scheme(pb.nx, flux=pb.flux, k=pb.k, stepper=pb.stepper, a=pb.a, eps=pb.eps, L=pb.L,
+                  numflux=getattr(pb, "numflux", 0))
 
 
 def phi(s: Scheme, dt: float, u_in, u_out, stream=None):
@@ -234,6 +239,22 @@ def cycle(s: Scheme, p: Params, u0, u, workspace=None, stream=None):
     iters = C.c_int32(0)
     rc = load().mgrit_cycle(C.byref(s), C.byref(p), _ptr(u0), _ptr(u), C.c_void_p(workspace.data_ptr()),
                             workspace.numel() * 8, hist, C.byref(iters), _stream(stream))
+    _check(rc, allow=(MGRIT_OK, MGRIT_NOT_CONVERGED))
+    n = iters.value
+    nres = 1 if p.levels == 1 else n + 1
+    return rc, [hist[i] for i in range(nres)], n
+
+
+def cycle_levels(schemes, p: Params, u0, u, workspace=None, stream=None):
+    """MGRIT with schemes[l] on level l; returns as :func:`cycle`."""
+    assert len(schemes) == p.levels
+    arr = (Scheme * len(schemes))(*schemes)
+    if workspace is None:
+        workspace = alloc_workspace(schemes[0], p)
+    hist = (C.c_double * (p.max_iter + 1))()
+    iters = C.c_int32(0)
+    rc = load().mgrit_cycle_levels(arr, C.byref(p), _ptr(u0), _ptr(u), C.c_void_p(workspace.data_ptr()),
+                                   workspace.numel() * 8, hist, C.byref(iters), _stream(stream))
     _check(rc, allow=(MGRIT_OK, MGRIT_NOT_CONVERGED))
     n = iters.value
     nres = 1 if p.levels == 1 else n + 1

@@ -81,3 +81,13 @@ extern "C" void hk_recon_vjp(const double* w, double eps, double umb, double upb
     for (int j = 0; j < 5; ++j) wb[j] = 0.0;
     weno5_cell_vjp(w[0], w[1], w[2], w[3], w[4], eps, umb, upb, wb);
 }
+
+// WENO3 / WENO7 reconstructions of the middle cell of a window of 2k+1 cells
+extern "C" void hk_recon_k(int k, const double* w, double eps, double* um, double* up)
+{
+    if (k == 1) weno3_cell(w[0], w[1], w[2], eps, *um, *up);
+    else weno7_cell(w[0], w[1], w[2], w[3], w[4], w[5], w[6], eps, *um, *up);
+}
+
+// the Roe flux with the Harten-Hyman fix (the kernels' twice-the-flux form, halved)
+extern "C" double hk_roe(double uL, double uR, double fa, double fb) { return 0.5 * roe_flux2(uL, uR, fa, fb); }

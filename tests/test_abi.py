@@ -54,7 +54,8 @@ def test_struct_layouts_match_header(tmp_path):
 
     src = tmp_path / "layout.c"
     checks = {
-        "mgrit_scheme": (mgrit.Scheme, ["flux", "k", "stepper", "nx", "a", "eps", "L", "alpha_fixed", "lf_dx_dt"]),
+        "mgrit_scheme": (mgrit.Scheme, ["flux", "k", "stepper", "nx", "a", "eps", "L", "alpha_fixed", "lf_dx_dt",
+                                        "numflux"]),
         "mgrit_params": (mgrit.Params, ["nt", "m", "levels", "relax", "cycle", "max_iter", "init", "coarse_guess",
                                         "storage", "sync_every", "dt", "tol", "coarse_integrator"]),
         "mgrit_profile_entry": (mgrit.ProfileEntry, ["launches", "ms", "phi_lines", "cell_steps"]),

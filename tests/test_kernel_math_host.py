@@ -103,3 +103,38 @@ def test_reconstruction_vjp_matches_oracle_gradient(hk, orc):
         hk.hk_recon_vjp(p(w), 1e-6, 0.0, 1.0, p(wb))
         ref = orc.weno5_left_grad(np.ascontiguousarray(w[::-1]), 1e-6)[::-1]
         assert np.max(np.abs(wb - ref)) <= 1e-9 * max(1.0, np.max(np.abs(ref))), (w, wb, ref)
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_weno3_weno7_cells_match_oracle(hk, orc, k):
+    """The kernels' WENO3 and WENO7 cell reconstructions (both faces) against
+    the oracle's, whose tables come from eq C, B and D."""
+    hk.hk_recon_k.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_double, C.POINTER(C.c_double),
+                              C.POINTER(C.c_double)]
+    n = 2 * k + 1
+    g = np.random.default_rng(30 + k)
+    windows = list(g.uniform(-1, 1, (300, n))) + list(W.shock_lines(2, 40, n))
+    windows += [np.array([0.0] * (k + 1) + [1.0] * k), np.array([1.0] * k + [0.0] * (k + 1)), np.full(n, 0.3)]
+    for w in windows:
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        um, up = C.c_double(), C.c_double()
+        hk.hk_recon_k(k, p(w), 1e-6, C.byref(um), C.byref(up))
+        ref_m = orc.weno_left(k, w, 1e-6)
+        ref_p = orc.weno_left(k, np.ascontiguousarray(w[::-1]), 1e-6)
+        scale = max(1.0, np.max(np.abs(w)))
+        assert abs(um.value - ref_m) < 1e-13 * scale, (w, um.value, ref_m)
+        assert abs(up.value - ref_p) < 1e-13 * scale, (w, up.value, ref_p)
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+def test_roe_flux_matches_oracle(hk, orc, flux):
+    hk.hk_roe.argtypes = [C.c_double] * 4
+    hk.hk_roe.restype = C.c_double
+    a = -0.7
+    fa, fb = flux_consts(flux, a)
+    s = orc.scheme(16, flux=flux, a=a, numflux=1)
+    g = np.random.default_rng(40 + flux)
+    pairs = [tuple(x) for x in g.uniform(-2, 2, (500, 2))] + [(-1.0, 1.0), (1.0, -1.0), (0.0, 0.0), (-0.5, 0.5)]
+    for uL, uR in pairs:
+        ref = orc.roe_flux(s, uL, uR)
+        assert abs(hk.hk_roe(uL, uR, fa, fb) - ref) < 1e-15 * (1 + uL * uL + uR * uR), (uL, uR)
