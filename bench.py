@@ -35,7 +35,7 @@ METRIC = "WENO5-SSPRK3 fine cell-steps/s in MGRIT relax; adjoint/forward time ra
 # divisions count as one flop
 FLOPS_PER_CELL_STEP = 440.0
 PEAK_FP64 = 78.6e12
-DOMINANT = "relax_fc_kernel<4, 4, 2, 3, false>"
+DOMINANT = "relax_fc_kernel<4, 4, 2, 3, false, false>"
 
 
 def measured_traffic(kernel):
@@ -55,6 +55,69 @@ def measured_traffic(kernel):
     except (OSError, KeyError, ValueError):
         return None
     return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
+def measured_variant_flops():
+    """Executed FP64 flops per cell-step of each scheme variant's level-0
+    F-sweep, from the SQ_INSTS_VALU_*_F64 counter record in
+    profiles/variant_flops.json (FMA = 2 flops, x 64 lanes), or None when the
+    record is missing or the kernel sources changed since it was taken."""
+    import hashlib
+
+    try:
+        with open(os.path.join(ROOT, "profiles", "variant_flops.json")) as f:
+            rec = json.load(f)
+        h = hashlib.sha256()
+        for name in rec["sources"]:
+            with open(os.path.join(ROOT, name), "rb") as f:
+                h.update(f.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["flops_per_cell_step"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
+def variant_rates():
+    """Row f3 measured: the level-0 F-sweep of the benchmark shape for every
+    reconstruction degree with the LF and the Roe flux."""
+    from paper_2104_09404_amd import profiling
+
+    rates = profiling.variants(reps=5, quiet=True)
+    flops = measured_variant_flops()
+    for name, r in rates.items():
+        f = flops.get(name) if flops else None
+        r["executed_flops_per_cell_step"] = f
+        r["tflops"] = f * r["cell_steps_per_s"] / 1e12 if f else None
+        r["frac_fp64_peak"] = f * r["cell_steps_per_s"] / PEAK_FP64 if f else None
+    return {"workload": "level-0 F-sweep of burgers_weno5_nx1024: 512 chunks x 7 SSPRK3 steps x 1024 cells",
+            "kernel": "relax_f_kernel<4, 4, k, 3, false, roe>", "variants": rates}
+
+
+def time_to_tolerance(mgrit):
+    """MGRIT wall time to a residual of 1e-10 where MGRIT converges (the
+    benchmark workload's coarse CFL of 51 makes it diverge, as the paper
+    finds for large coarse CFL): the first-order workload and the paper's
+    high-order experiment with WENO5 + LF."""
+    import torch
+
+    from paper_2104_09404_amd import workloads as W
+
+    out = {}
+    for pb in (W.w0_burgers_k0(), W.e4_high_order(2, 0)):
+        s = mgrit.scheme_from_problem(pb)
+        u0 = torch.from_numpy(pb.u0).cuda()
+        u = torch.zeros((pb.nt + 1, pb.nx), dtype=torch.float64, device="cuda")
+        p = mgrit.params(pb.nt, pb.dt, pb.m, pb.levels, relax=pb.relax, max_iter=max(pb.max_iter, 100),
+                         tol=1e-10, sync_every=1)
+        ws = mgrit.alloc_workspace(s, p)
+        mgrit.cycle(s, p, u0, u, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, hist, n = mgrit.cycle(s, p, u0, u, ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out[pb.name] = {"ms": ms, "cycles": n, "converged": rc == 0, "residual": hist[-1],
+                        "gpu_serial_ms": gpu_serial_ms(mgrit, s, pb, u0)}
+    return out
 
 
 def gpu_serial_ms(mgrit, s, pb, u0, reps=3):
@@ -82,6 +145,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the reference-oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the scheme-variant sweeps")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio (its split-line launches are cooperative)")
     return ap.parse_args()
@@ -187,14 +251,22 @@ def main():
         mgrit.cycle(s, params(args.warmup), u0, u, ws)
     torch.cuda.synchronize()
 
-    # timed region: K iterations, kernel events on
-    mgrit.set_profiling(True)
+    # timed region: K iterations; HIP events bracket the dominant kernel only
+    # (every event pair costs stream time), the other kernels are counted
+    mgrit.set_profiling(True, classes=["relax_fc_l0"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rc, hist, n = mgrit.cycle(s, params(args.steps), u0, u, ws)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = mgrit.get_profile()
+    mgrit.set_profiling(False)
+    # per-kernel breakdown: the same K iterations again, outside the timed
+    # region, with events on every kernel
+    mgrit.set_profiling(True)
+    mgrit.cycle(s, params(args.steps), u0, u, ws)
+    torch.cuda.synchronize()
+    breakdown = mgrit.get_profile()
     mgrit.set_profiling(False)
 
     cells = sum(v["cell_steps"] for v in prof.values())
@@ -204,8 +276,8 @@ def main():
     dom_flops = FLOPS_PER_CELL_STEP * dom["cell_steps"] / max(dom["launches"], 1)
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     relax_classes = ["relax_fc_l0", "relax_fr_l0", "relax_fc_coarse", "relax_fr_coarse", "interp"]
-    relax_cells = sum(prof[c]["cell_steps"] for c in relax_classes)
-    relax_ms = sum(prof[c]["ms"] for c in relax_classes)
+    relax_cells = sum(breakdown[c]["cell_steps"] for c in relax_classes)
+    relax_ms = sum(breakdown[c]["ms"] for c in relax_classes)
 
     out = {
         "metric": METRIC,
@@ -238,12 +310,17 @@ def main():
             "avg_launch_ms": dom_ms,
         },
         "relax_cell_steps_per_s": relax_cells / (relax_ms * 1e-3) if relax_ms > 0 else None,
-        "level0_relax_cell_steps_per_s": (prof["relax_fc_l0"]["cell_steps"] + prof["relax_fr_l0"]["cell_steps"])
-        / ((prof["relax_fc_l0"]["ms"] + prof["relax_fr_l0"]["ms"]) * 1e-3),
-        "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items() if v["launches"]},
+        "level0_relax_cell_steps_per_s": (breakdown["relax_fc_l0"]["cell_steps"]
+                                          + breakdown["relax_fr_l0"]["cell_steps"])
+        / ((breakdown["relax_fc_l0"]["ms"] + breakdown["relax_fr_l0"]["ms"]) * 1e-3),
+        "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in breakdown.items() if v["launches"]},
+        "breakdown_note": "relax_*_per_s and kernel_ms_per_step come from a second run of the same K cycles "
+                          "with events on every kernel, outside the timed region",
         "adjoint_forward_ratio": None if args.no_adjoint else adjoint_ratio(mgrit),
         "mgrit_converges": bool(np.isfinite(hist[-1]) and hist[-1] < 1e-10),
         "gpu_serial_ms": gpu_serial_ms(mgrit, s, pb, u0),
+        "time_to_tolerance": time_to_tolerance(mgrit),
+        "scheme_variants": None if args.no_variants else variant_rates(),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb, args.cpu_seconds)

@@ -323,6 +323,13 @@ typedef struct {
 void mgrit_set_profiling(int on);
 int mgrit_get_profile(mgrit_profile_entry* out, int cap);
 
+/* With profiling on, bracket only the launches of the kernel classes whose
+   bit (1 << MGRIT_KC_*) is set in `classes` with events; the other classes
+   still count launches, Phi lines and cell steps, with ms = 0.  Each event
+   pair costs stream time between kernels, so a timing run keeps the events
+   to the kernel it measures.  Default: every class.  Not thread safe. */
+void mgrit_set_profiling_mask(uint32_t classes);
+
 /* kernel configuration chosen for `nlines` lines of `nx` cells in one launch
    (one workgroup per line): cells per thread and waves per line.  Launches of
    fewer than 256 lines count as latency bound and get more threads per line.
@@ -342,11 +349,32 @@ int mgrit_tiled_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves, in
 int mgrit_set_tiled_config(int32_t nx_lo, int32_t nx_hi, int32_t cells_per_thread, int32_t waves);
 
 /* override the configuration for line lengths nx_lo..nx_hi in latency-bound
-   (latency != 0) or throughput launches (used by the autotuner); the pair must
-   be compiled and cover nx_hi.  cells_per_thread == 0 clears every override.
-   Not thread safe. */
+   (latency != 0) or throughput launches (mgrit_autotune installs its choice
+   this way); the pair must be compiled and cover nx_hi.  cells_per_thread ==
+   0 clears every override.  Batches keep to the pairs compiled for them and
+   take the measured default when an override names another.  Not thread
+   safe. */
 int mgrit_set_kernel_config(int32_t nx_lo, int32_t nx_hi, int32_t latency, int32_t cells_per_thread,
                             int32_t waves);
+
+/*
+ * Autotuner of the launch shape (not in the paper): times nsteps applications
+ * of Phi with scheme s on nlines independent lines, one workgroup per line,
+ * for every compiled (cells per thread, waves) pair whose workgroup covers
+ * the line without being more than 4x larger, and picks the fastest (median
+ * of three launches after one warm-up, HIP events on `stream`).  With
+ * install != 0 the choice becomes the override for lines of exactly s->nx
+ * cells in the regime of nlines (latency bound below 256 lines, else
+ * throughput), as mgrit_set_kernel_config would set it.
+ *   scratch  device, at least mgrit_autotune_scratch_bytes(s->nx, nlines)
+ *            bytes, caller-owned; overwritten with smooth test lines.
+ *   cells_per_thread, waves, ms_best  HOST outputs (each may be NULL).
+ * Synchronises the stream.  Lines longer than one workgroup holds return
+ * MGRIT_EUNSUPPORTED.  Not thread safe when installing.
+ */
+size_t mgrit_autotune_scratch_bytes(int32_t nx, int32_t nlines);
+int mgrit_autotune(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, void* scratch, size_t scratch_bytes,
+                   int32_t install, int32_t* cells_per_thread, int32_t* waves, float* ms_best, void* stream);
 
 /*
  * Batches of independent problems (many initial-value problems solved by

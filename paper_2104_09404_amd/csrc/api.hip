@@ -63,6 +63,15 @@ struct Override {
 };
 std::vector<Override> g_overrides;
 
+bool batch_cfg_compiled(const KernelCfg& c)
+{
+#define MGK_ENTRY(C, W) \
+    if (c.cpt == C && c.nw == W) return true;
+    MGK_BATCH_CFG_LIST(MGK_ENTRY)
+#undef MGK_ENTRY
+    return false;
+}
+
 bool cfg_compiled(int cpt, int nw)
 {
     for (int i = 0; i < kNumCfgs; ++i)
@@ -74,6 +83,8 @@ bool cfg_compiled(int cpt, int nw)
 // fill the 256 compute units with one workgroup per line).
 const int kLatencyLines = 256;
 
+bool choose_cfg_default(int nx, int nlines, KernelCfg* out);
+
 bool choose_cfg(int nx, int nlines, KernelCfg* out)
 {
     const bool latency = nlines < kLatencyLines;
@@ -82,6 +93,13 @@ bool choose_cfg(int nx, int nlines, KernelCfg* out)
             *out = o.cfg;
             return true;
         }
+    return choose_cfg_default(nx, nlines, out);
+}
+
+// the measured preference tables, without overrides
+bool choose_cfg_default(int nx, int nlines, KernelCfg* out)
+{
+    const bool latency = nlines < kLatencyLines;
     if (nx > kMaxLine) return false;
     if (latency) {
         // per-step latency of a single line, measured on MI355X (1024 cells:
@@ -327,8 +345,45 @@ struct PendingEvent {
     double phi_lines, cells;
 };
 bool g_prof = false;
+uint32_t g_prof_mask = 0xffffffffu;  // kernel classes whose launches are bracketed by events
 mgrit_profile_entry g_prof_acc[MGRIT_KC_COUNT];
 std::vector<PendingEvent> g_pending;
+
+// Profiling of one launch: every class counts launches, Phi lines and cell
+// steps; only the classes in g_prof_mask are bracketed by HIP events (the
+// events themselves cost stream time, so a timing run can keep them to the
+// kernel it measures).
+struct ProfLaunch {
+    PendingEvent pe;
+    bool timed = false;
+    int begin(int kc, double phi_lines, double cells, hipStream_t st)
+    {
+        if (!g_prof) return MGRIT_OK;
+        pe.kc = kc;
+        pe.phi_lines = phi_lines;
+        pe.cells = cells;
+        timed = ((g_prof_mask >> kc) & 1u) != 0;
+        if (!timed) return MGRIT_OK;
+        HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
+        HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
+        HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
+        return MGRIT_OK;
+    }
+    int end(hipStream_t st)
+    {
+        if (!g_prof) return MGRIT_OK;
+        if (timed) {
+            HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
+            g_pending.push_back(pe);
+        } else {
+            mgrit_profile_entry& acc = g_prof_acc[pe.kc];
+            acc.launches += 1;
+            acc.phi_lines += pe.phi_lines;
+            acc.cell_steps += pe.cells;
+        }
+        return MGRIT_OK;
+    }
+};
 
 // A batch records the sweeps of one cycle per problem instead of launching them
 struct Recorded {
@@ -374,23 +429,13 @@ int launch(int kc, const SweepArgs& a_in, const mgrit_scheme* s, hipStream_t st,
     } else if (!choose_cfg(s->nx, a.nchunks, &cfg)) {
         return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", s->nx);
     }
-    PendingEvent pe;
-    if (g_prof) {
-        pe.kc = kc;
-        pe.phi_lines = phi_lines;
-        pe.cells = phi_lines * (double)s->nx;
-        HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
-        HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
-        HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
-    }
+    ProfLaunch pl;
+    int rc = pl.begin(kc, phi_lines, phi_lines * (double)s->nx, st);
+    if (rc) return rc;
     hipError_t e = tiled ? mgk::launch_tiled(a, cfg, s->k, s->stepper, st)
                          : mgk::launch_sweep(a, cfg, s->k, s->stepper, st);
     if (e != hipSuccess) return hip_fail(e, tiled ? "tiled sweep kernel launch" : "sweep kernel launch");
-    if (g_prof) {
-        HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
-        g_pending.push_back(pe);
-    }
-    return MGRIT_OK;
+    return pl.end(st);
 }
 
 int launch_adj(int kc, const mgk::AdjArgs& a, const mgrit_scheme* s, int store_mode, hipStream_t st, double cells)
@@ -399,22 +444,12 @@ int launch_adj(int kc, const mgk::AdjArgs& a, const mgrit_scheme* s, int store_m
     if (!choose_adj_cfg(s->nx, &cfg))
         return fail(MGRIT_EUNSUPPORTED, "adjoint: nx = %d is not supported (at most %d cells, even above 512)", s->nx,
                     kMaxAdjLine);
-    PendingEvent pe;
-    if (g_prof) {
-        pe.kc = kc;
-        pe.phi_lines = cells / (double)s->nx;
-        pe.cells = cells;
-        HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
-        HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
-        HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
-    }
+    ProfLaunch pl;
+    int rc = pl.begin(kc, cells / (double)s->nx, cells, st);
+    if (rc) return rc;
     hipError_t e = mgk::launch_adjoint(a, cfg, s->k, s->stepper, store_mode, st);
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
-    if (g_prof) {
-        HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
-        g_pending.push_back(pe);
-    }
-    return MGRIT_OK;
+    return pl.end(st);
 }
 
 // Two ints of pinned host memory per calling thread, allocated on the thread's
@@ -430,22 +465,12 @@ int* pinned_flags()
 template <class F>
 int launch_aux(F&& f, hipStream_t st)
 {
-    PendingEvent pe;
-    if (g_prof) {
-        pe.kc = MGRIT_KC_AUX;
-        pe.phi_lines = 0;
-        pe.cells = 0;
-        HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
-        HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
-        HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
-    }
+    ProfLaunch pl;
+    int rc = pl.begin(MGRIT_KC_AUX, 0.0, 0.0, st);
+    if (rc) return rc;
     hipError_t e = f();
     if (e != hipSuccess) return hip_fail(e, "auxiliary kernel launch");
-    if (g_prof) {
-        HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
-        g_pending.push_back(pe);
-    }
-    return MGRIT_OK;
+    return pl.end(st);
 }
 
 int drain_profile()
@@ -769,6 +794,8 @@ void mgrit_set_profiling(int on)
     g_pending.clear();
 }
 
+void mgrit_set_profiling_mask(uint32_t classes) { g_prof_mask = classes; }
+
 int mgrit_get_profile(mgrit_profile_entry* out, int cap)
 {
     int rc = drain_profile();
@@ -784,6 +811,77 @@ int mgrit_kernel_config(int32_t nx, int32_t nlines, int32_t* cells_per_thread, i
     if (!choose_cfg(nx, nlines, &c)) return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", nx);
     if (cells_per_thread) *cells_per_thread = c.cpt;
     if (waves) *waves = c.nw;
+    return MGRIT_OK;
+}
+
+size_t mgrit_autotune_scratch_bytes(int32_t nx, int32_t nlines)
+{
+    if (nx < 8 || nlines < 1) return 0;
+    return align256(sizeof(double) * (size_t)nx * (size_t)nlines);
+}
+
+int mgrit_autotune(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, void* scratch, size_t scratch_bytes,
+                   int32_t install, int32_t* cells_per_thread, int32_t* waves, float* ms_best, void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if (nlines < 1 || nsteps < 1) return fail(MGRIT_EINVAL, "nlines and nsteps must be >= 1");
+    if (scratch == nullptr || scratch_bytes < mgrit_autotune_scratch_bytes(s->nx, nlines))
+        return fail(MGRIT_EINVAL, "scratch must hold nlines x nx doubles");
+    hipStream_t st = (hipStream_t)stream;
+    double* lines = (double*)scratch;
+    HIP_TRY(mgk::launch_fill_wave(lines, s->nx, nlines, st), "fill kernel launch");
+    // CFL 0.5 for the data's speed 0.75 (Burgers) or |a| (advection)
+    const double dx = s->L / (double)s->nx;
+    const double speed = (s->flux == 0) ? 0.75 : (std::fabs(s->a) > 0.0 ? std::fabs(s->a) : 1.0);
+    const double dt = 0.5 * dx / speed;
+    SweepArgs a = base_args(s);
+    a.nchunks = nlines;
+    a.m = 0;
+    a.nsteps = nsteps;
+    a.end_mode = mgk::END_NONE;
+    a.dt = dt;
+    a.ustart = lines;
+    a.ustart_stride = 1;  // nothing is stored: the lines stay as filled
+    a.pc = phi_const(s, dt);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    float best = -1.f;
+    KernelCfg best_cfg{0, 0};
+    for (int i = 0; i < kNumCfgs && rc == MGRIT_OK; ++i) {
+        const KernelCfg c = kCfgs[i];
+        const int cap = 64 * c.cpt * c.nw;
+        if (cap < s->nx || cap > 4 * (s->nx > 64 ? s->nx : 64)) continue;  // covers the line, not mostly idle
+        float t[3];
+        for (int r = 0; r < 4 && rc == MGRIT_OK; ++r) {  // one warm-up, three timed
+            hipError_t e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = mgk::launch_sweep(a, c, s->k, s->stepper, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) rc = hip_fail(e, "autotune launch");
+            else if (r > 0) t[r - 1] = ms;
+        }
+        if (rc) break;
+        std::sort(t, t + 3);
+        if (best < 0.f || t[1] < best) {
+            best = t[1];
+            best_cfg = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (best < 0.f) return fail(MGRIT_EUNSUPPORTED, "no one-workgroup configuration covers nx = %d", s->nx);
+    if (install) {
+        const bool latency = nlines < kLatencyLines;
+        g_overrides.insert(g_overrides.begin(), Override{s->nx, s->nx, latency, best_cfg});
+    }
+    if (cells_per_thread) *cells_per_thread = best_cfg.cpt;
+    if (waves) *waves = best_cfg.nw;
+    if (ms_best) *ms_best = best;
     return MGRIT_OK;
 }
 
@@ -1068,22 +1166,12 @@ int mgrit_adjoint(const mgrit_scheme* s, double dt, int32_t nt, int32_t every, i
     auto run = [&](int kc, mgk::AdjArgs& a, int store_mode, double cells) -> int {
         if (!split) return launch_adj(kc, a, s, store_mode, st, cells);
         tile_args(a);
-        PendingEvent pe;
-        if (g_prof) {
-            pe.kc = kc;
-            pe.phi_lines = cells / (double)nx;
-            pe.cells = cells;
-            HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
-            HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
-            HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
-        }
+        ProfLaunch pl;
+        int prc = pl.begin(kc, cells / (double)nx, cells, st);
+        if (prc) return prc;
         hipError_t e = mgk::launch_tiled_adjoint(a, cfg, s->k, s->stepper, store_mode, st);
         if (e != hipSuccess) return hip_fail(e, "split-line adjoint kernel launch");
-        if (g_prof) {
-            HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
-            g_pending.push_back(pe);
-        }
-        return MGRIT_OK;
+        return pl.end(st);
     };
     const int nbatch = (nseg + P - 1) / P;
     const double* lam_cur = lambda_T;
@@ -1313,6 +1401,7 @@ const int kMaxBatchSerialLine = 64 * 16 * 8;
 struct BatchBucket {
     KernelCfg cfg;
     int ragged;
+    int roe;                 // numerical flux of every problem in the bucket
     std::vector<int> probs;  // problem indices
     std::vector<int> offset;
     int nblocks;
@@ -1463,13 +1552,18 @@ int plan_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p,
                     const int nl = serial ? 1 : (int)std::min<long long>(total_lines, 1 << 30);
                     if (!choose_cfg(probs[i].scheme.nx, nl, &c))
                         return fail(MGRIT_EUNSUPPORTED, "problem %d: no kernel configuration", i);
+                    // an override outside the configurations compiled for batches
+                    // gives way to the measured default
+                    if (!batch_cfg_compiled(c) && !choose_cfg_default(probs[i].scheme.nx, nl, &c))
+                        return fail(MGRIT_EUNSUPPORTED, "problem %d: no kernel configuration", i);
                 }
                 const int rag = (c.cpt > 1 && probs[i].scheme.nx % c.cpt != 0) ? 1 : 0;
+                const int roe = probs[i].scheme.numflux;
                 BatchBucket* bk = nullptr;
                 for (BatchBucket& b : P.buckets)
-                    if (b.cfg.cpt == c.cpt && b.cfg.nw == c.nw && b.ragged == rag) bk = &b;
+                    if (b.cfg.cpt == c.cpt && b.cfg.nw == c.nw && b.ragged == rag && b.roe == roe) bk = &b;
                 if (bk == nullptr) {
-                    P.buckets.push_back(BatchBucket{c, rag, {}, {}, 0, 0});
+                    P.buckets.push_back(BatchBucket{c, rag, roe, {}, {}, 0, 0});
                     bk = &P.buckets.back();
                 }
                 bk->offset.push_back(bk->nblocks);
@@ -1584,26 +1678,22 @@ int mgrit_cycle_batched(const mgrit_problem* probs, int32_t count, const mgrit_p
                 t.nblocks = b.nblocks;
                 t.end_mode = P.end_mode;
                 t.ragged = b.ragged;
-                PendingEvent pe;
+                t.roe = b.roe;
+                t.pad_ = 0;
+                double phi_lines = 0.0, cells = 0.0;
                 if (g_prof) {
-                    pe.kc = P.kc;
-                    pe.phi_lines = 0;
-                    pe.cells = 0;
                     for (int i : b.probs) {
                         const double phi = bp.host_phi[(base_index + ph) * count + i];
-                        pe.phi_lines += phi;
-                        pe.cells += phi * (double)probs[i].scheme.nx;
+                        phi_lines += phi;
+                        cells += phi * (double)probs[i].scheme.nx;
                     }
-                    HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
-                    HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
-                    HIP_TRY(hipEventRecord(pe.e0, st), "hipEventRecord");
                 }
+                ProfLaunch pl;
+                int prc = pl.begin(P.kc, phi_lines, cells, st);
+                if (prc) return prc;
                 hipError_t e = mgk::launch_batch(t, b.cfg, k0, st0, st);
                 if (e != hipSuccess) return hip_fail(e, "batched sweep kernel launch");
-                if (g_prof) {
-                    HIP_TRY(hipEventRecord(pe.e1, st), "hipEventRecord");
-                    g_pending.push_back(pe);
-                }
+                if ((prc = pl.end(st))) return prc;
             }
             for (int i : P.split) {
                 const SweepArgs& a = bp.host_args[(base_index + ph) * count + i];

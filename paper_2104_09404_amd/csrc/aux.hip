@@ -178,6 +178,25 @@ hipError_t launch_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int s
     }
 }
 
+// smooth test lines for timing runs: u[b][i] = 0.5 + 0.25 sin(2 pi (i + 1/2)/nx + 0.1 b)
+__global__ void fill_wave_kernel(double* u, int64_t nx, int64_t nlines)
+{
+    const int64_t total = nx * nlines;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / nx, c = i - b * nx;
+        u[i] = 0.5 + 0.25 * sin(2.0 * M_PI * ((double)c + 0.5) / (double)nx + 0.1 * (double)b);
+    }
+}
+
+hipError_t launch_fill_wave(double* u, int64_t nx, int64_t nlines, hipStream_t s)
+{
+    if (nlines <= 0) return hipSuccess;
+    int64_t blocks = (nx * nlines + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fill_wave_kernel, dim3((unsigned)blocks), dim3(256), 0, s, u, nx, nlines);
+    return hipGetLastError();
+}
+
 hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s)
 {
     if (nlines <= 0) return hipSuccess;

@@ -90,6 +90,8 @@ struct BatchLaunch {
     int nblocks;
     int end_mode;        // END_NONE, END_CSTEP or END_RESTRICT (every entry of args has it)
     int ragged;          // some problem's line is not a multiple of the cells per thread
+    int roe;             // every problem of the launch uses the Roe flux (else LF)
+    int pad_;
 };
 
 // per-problem residual reduction of a batch
@@ -227,6 +229,7 @@ hipError_t launch_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int ste
 hipError_t launch_tiled_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int stepper, int store_mode,
                                 hipStream_t s);
 hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s);
+hipError_t launch_fill_wave(double* u, int64_t nx, int64_t nlines, hipStream_t s);
 hipError_t launch_clear_ints(int* p, int n, hipStream_t s);
 hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_t s);
 hipError_t launch_reduce_norm(const double* partial, int n, double* hist, int* counter, int* flag, double tol,

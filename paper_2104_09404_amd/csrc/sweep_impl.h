@@ -177,13 +177,14 @@ __device__ __forceinline__ void reconstruct(const double (&w)[CPT + 6], double e
 }
 
 // A(V) for the thread's cells: eq spaceDisc with the LF flux (eq LFflux) or,
-// when pc.roe is set, the Roe flux with the Harten-Hyman fix (eq roeflux),
-// and a WENO reconstruction of degree K.
+// with ROE, the Roe flux with the Harten-Hyman fix (eq roeflux), and a WENO
+// reconstruction of degree K.
 // RAG: the line length is not a multiple of CPT, so one thread is ragged.
 // par selects the alpha_LF slots of this stage (the other half is still read
 // by slow waves of the previous stage until the first barrier).  The Roe flux
-// is local to its interface: no reduction, pc.roe is uniform over the launch.
-template <int CPT, int NW, int K, bool RAG>
+// is local to its interface: no reduction.  The flux is a compile-time choice:
+// a run-time one lets the compiler duplicate whole step loops per flux.
+template <int CPT, int NW, int K, bool RAG, bool ROE = false>
 __device__ __forceinline__ void op_A(const double (&V)[CPT], double (&A)[CPT], const Geo<CPT, NW>& g,
                                      const Smem<CPT, NW>& sm, const PhiConst& pc, int& par)
 {
@@ -219,7 +220,7 @@ __device__ __forceinline__ void op_A(const double (&V)[CPT], double (&A)[CPT], c
     sm.bm[g.t] = last;
     sm.bp[g.t] = up[0];
     double F[CPT + 1];
-    if (pc.roe) {
+    if constexpr (ROE) {
         __syncthreads();
         const double uml = sm.bm[g.left];
         const double upr = sm.bp[g.right];
@@ -263,34 +264,34 @@ __device__ __forceinline__ void op_A(const double (&V)[CPT], double (&A)[CPT], c
 }
 
 // x <- Phi(x) with step dt (eq SSPRK1/2/3)
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE = false>
 __device__ __forceinline__ void phi(double (&x)[CPT], double dt, const Geo<CPT, NW>& g, const Smem<CPT, NW>& sm,
                                     const PhiConst& pc, int& par)
 {
     double A[CPT];
     if (ST == 1) {
-        op_A<CPT, NW, K, RAG>(x, A, g, sm, pc, par);
+        op_A<CPT, NW, K, RAG, ROE>(x, A, g, sm, pc, par);
 #pragma unroll
         for (int q = 0; q < CPT; ++q) x[q] = rk_first(x[q], A[q], dt);
     } else if (ST == 2) {
         double v[CPT];
-        op_A<CPT, NW, K, RAG>(x, A, g, sm, pc, par);
+        op_A<CPT, NW, K, RAG, ROE>(x, A, g, sm, pc, par);
 #pragma unroll
         for (int q = 0; q < CPT; ++q) v[q] = rk_first(x[q], A[q], dt);
-        op_A<CPT, NW, K, RAG>(v, A, g, sm, pc, par);
+        op_A<CPT, NW, K, RAG, ROE>(v, A, g, sm, pc, par);
         const double hdt = 0.5 * dt;
 #pragma unroll
         for (int q = 0; q < CPT; ++q) x[q] = rk2_second(x[q], v[q], A[q], hdt);
     } else {
         double v[CPT];
-        op_A<CPT, NW, K, RAG>(x, A, g, sm, pc, par);
+        op_A<CPT, NW, K, RAG, ROE>(x, A, g, sm, pc, par);
 #pragma unroll
         for (int q = 0; q < CPT; ++q) v[q] = rk_first(x[q], A[q], dt);
-        op_A<CPT, NW, K, RAG>(v, A, g, sm, pc, par);
+        op_A<CPT, NW, K, RAG, ROE>(v, A, g, sm, pc, par);
         const double qdt = 0.25 * dt;
 #pragma unroll
         for (int q = 0; q < CPT; ++q) v[q] = rk3_second(x[q], v[q], A[q], qdt);
-        op_A<CPT, NW, K, RAG>(v, A, g, sm, pc, par);
+        op_A<CPT, NW, K, RAG, ROE>(v, A, g, sm, pc, par);
         const double tdt = (2.0 / 3.0) * dt;
 #pragma unroll
         for (int q = 0; q < CPT; ++q) x[q] = rk3_third(x[q], v[q], A[q], tdt);
@@ -370,7 +371,7 @@ __device__ __forceinline__ void psi(double (&x)[CPT], int order, int M, double d
 }
 
 // one step of the level: Phi, or the matching coarse integrator of M fine steps
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __device__ __forceinline__ void level_step(double (&x)[CPT], double dt, int M, const SweepArgs& a,
                                            const Geo<CPT, NW>& g, const Smem<CPT, NW>& sm, const PhiConst& pc,
                                            int& par)
@@ -381,7 +382,7 @@ __device__ __forceinline__ void level_step(double (&x)[CPT], double dt, int M, c
             return;
         }
     }
-    phi<CPT, NW, K, ST, RAG>(x, dt, g, sm, pc, par);
+    phi<CPT, NW, K, ST, RAG, ROE>(x, dt, g, sm, pc, par);
 }
 
 template <int CPT, int NW>
@@ -453,9 +454,9 @@ __device__ __forceinline__ double line_sqdiff(const double (&a)[CPT], const doub
 }
 
 // One chunk (one line) per workgroup.  See SweepArgs for the roles; END is
-// the compile-time end mode.
-template <int CPT, int NW, int K, int ST, bool RAG, int END>
-__device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
+// the compile-time end mode, ROE the numerical flux.
+template <int CPT, int NW, int K, int ST, bool RAG, int END, bool ROE>
+__device__ __forceinline__ void sweep_body_t(const SweepArgs& a, const int c)
 {
     if (a.flag != nullptr && *a.flag != 0) return;
     extern __shared__ double smem_raw[];
@@ -487,7 +488,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
 
     const int64_t n0 = (int64_t)c * a.m;
     for (int j = 1; j <= a.nsteps; ++j) {
-        level_step<CPT, NW, K, ST, RAG>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
+        level_step<CPT, NW, K, ST, RAG, ROE>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
         if (a.g != nullptr) add_line(x, a.g + (n0 + j) * nx, g);
         if (a.fout != nullptr) {
             if (a.fout_every <= 1) store_line(x, a.fout + (n0 + j) * nx, g);
@@ -497,7 +498,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
 
     if constexpr (END == END_NONE) return;
     if constexpr (END == END_PHI) {
-        level_step<CPT, NW, K, ST, RAG>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
+        level_step<CPT, NW, K, ST, RAG, ROE>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
         if (a.gc_sub != nullptr) {
             // the second half of a split FAS restriction: g_c = t - Phi_{l+1}(chunk start)
             double* out = a.gc_sub + (int64_t)(c + 1) * nx;
@@ -513,7 +514,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
     }
     // one more step to the chunk's end C-point n1 = (c+1) m
     const int64_t n1 = n0 + a.m;
-    level_step<CPT, NW, K, ST, RAG>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
+    level_step<CPT, NW, K, ST, RAG, ROE>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
     if (a.g != nullptr) add_line(x, a.g + n1 * nx, g);
     // the current value at that C-point
     const double* cnext = a.cref + (int64_t)(c + 1) * a.cref_stride * nx;
@@ -541,7 +542,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
     load_line(y, cstart, g);
     PhiConst pcn = a.pc;
     if (a.alpha_next > 0.0) pcn.alpha_fixed = a.alpha_next;
-    level_step<CPT, NW, K, ST, RAG>(y, a.dt_next, a.psi_M_next, a, g, sm, pcn, par);
+    level_step<CPT, NW, K, ST, RAG, ROE>(y, a.dt_next, a.psi_M_next, a, g, sm, pcn, par);
     if (g.active) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) y[q] = x[q] - y[q];
@@ -550,38 +551,40 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, const int c)
 }
 
 
-// The four roles as separately named kernels (so that profiles tell them apart)
-template <int CPT, int NW, int K, int ST, bool RAG>
+// The four roles as separately named kernels (so that profiles tell them
+// apart); ROE (the numerical flux) is a kernel parameter, so that each flux
+// gets its own code and register allocation
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __global__ __launch_bounds__(64 * NW) void relax_f_kernel(SweepArgs a)
 {
-    sweep_body<CPT, NW, K, ST, RAG, END_NONE>(a, blockIdx.x);
+    sweep_body_t<CPT, NW, K, ST, RAG, END_NONE, ROE>(a, blockIdx.x);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __global__ __launch_bounds__(64 * NW) void relax_fc_kernel(SweepArgs a)
 {
-    sweep_body<CPT, NW, K, ST, RAG, END_CSTEP>(a, blockIdx.x);
+    sweep_body_t<CPT, NW, K, ST, RAG, END_CSTEP, ROE>(a, blockIdx.x);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __global__ __launch_bounds__(64 * NW) void relax_fr_kernel(SweepArgs a)
 {
-    sweep_body<CPT, NW, K, ST, RAG, END_RESTRICT>(a, blockIdx.x);
+    sweep_body_t<CPT, NW, K, ST, RAG, END_RESTRICT, ROE>(a, blockIdx.x);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __global__ __launch_bounds__(64 * NW) void phi_kernel(SweepArgs a)
 {
-    sweep_body<CPT, NW, K, ST, RAG, END_PHI>(a, blockIdx.x);
+    sweep_body_t<CPT, NW, K, ST, RAG, END_PHI, ROE>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // batches of independent problems: one launch covers the chunks of every
-// problem of a bucket (problems sharing a configuration); workgroup b finds
-// its problem by binary search over the bucket's chunk offsets and takes that
-// problem's arguments from a device table
+// problem of a bucket (problems sharing a configuration and a numerical
+// flux); workgroup b finds its problem by binary search over the bucket's
+// chunk offsets and takes that problem's arguments from a device table
 // ---------------------------------------------------------------------------
-template <int CPT, int NW, int K, int ST, bool RAG, int END>
+template <int CPT, int NW, int K, int ST, bool RAG, int END, bool ROE>
 __device__ __forceinline__ void batch_body(const BatchLaunch& t)
 {
     const int b = blockIdx.x;
@@ -592,27 +595,26 @@ __device__ __forceinline__ void batch_body(const BatchLaunch& t)
         else hi = mid - 1;
     }
     const SweepArgs a = t.args[t.problem[lo]];
-    sweep_body<CPT, NW, K, ST, RAG, END>(a, b - t.offset[lo]);
+    sweep_body_t<CPT, NW, K, ST, RAG, END, ROE>(a, b - t.offset[lo]);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __global__ __launch_bounds__(64 * NW) void batch_f_kernel(BatchLaunch t)
 {
-    batch_body<CPT, NW, K, ST, RAG, END_NONE>(t);
+    batch_body<CPT, NW, K, ST, RAG, END_NONE, ROE>(t);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __global__ __launch_bounds__(64 * NW) void batch_fc_kernel(BatchLaunch t)
 {
-    batch_body<CPT, NW, K, ST, RAG, END_CSTEP>(t);
+    batch_body<CPT, NW, K, ST, RAG, END_CSTEP, ROE>(t);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __global__ __launch_bounds__(64 * NW) void batch_fr_kernel(BatchLaunch t)
 {
-    batch_body<CPT, NW, K, ST, RAG, END_RESTRICT>(t);
+    batch_body<CPT, NW, K, ST, RAG, END_RESTRICT, ROE>(t);
 }
-
 template <class Fn>
 static hipError_t launch_batch_fn(Fn fn, const BatchLaunch& t, int nw, size_t shmem, hipStream_t s)
 {
@@ -624,16 +626,23 @@ static hipError_t launch_batch_fn(Fn fn, const BatchLaunch& t, int nw, size_t sh
     return hipGetLastError();
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
-static hipError_t launch_batch_role(const BatchLaunch& t, hipStream_t s)
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
+static hipError_t launch_batch_role_f(const BatchLaunch& t, hipStream_t s)
 {
     const size_t shmem = smem_bytes(CPT, NW);
     switch (t.end_mode) {
-    case END_NONE: return launch_batch_fn(batch_f_kernel<CPT, NW, K, ST, RAG>, t, NW, shmem, s);
-    case END_CSTEP: return launch_batch_fn(batch_fc_kernel<CPT, NW, K, ST, RAG>, t, NW, shmem, s);
-    case END_RESTRICT: return launch_batch_fn(batch_fr_kernel<CPT, NW, K, ST, RAG>, t, NW, shmem, s);
+    case END_NONE: return launch_batch_fn(batch_f_kernel<CPT, NW, K, ST, RAG, ROE>, t, NW, shmem, s);
+    case END_CSTEP: return launch_batch_fn(batch_fc_kernel<CPT, NW, K, ST, RAG, ROE>, t, NW, shmem, s);
+    case END_RESTRICT: return launch_batch_fn(batch_fr_kernel<CPT, NW, K, ST, RAG, ROE>, t, NW, shmem, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG>
+static hipError_t launch_batch_role(const BatchLaunch& t, hipStream_t s)
+{
+    if (t.roe) return launch_batch_role_f<CPT, NW, K, ST, RAG, true>(t, s);
+    return launch_batch_role_f<CPT, NW, K, ST, RAG, false>(t, s);
 }
 
 template <int K, int ST>
@@ -645,8 +654,12 @@ hipError_t launch_batch_ks(const BatchLaunch& t, const KernelCfg& cfg, hipStream
         // roles spill registers at this size)
         if (t.end_mode != END_NONE) return hipErrorInvalidValue;
         const size_t shmem = smem_bytes(8, 16);
-        if (t.ragged) return launch_batch_fn(batch_f_kernel<8, 16, K, ST, true>, t, 16, shmem, s);
-        return launch_batch_fn(batch_f_kernel<8, 16, K, ST, false>, t, 16, shmem, s);
+        if (t.roe) {
+            if (t.ragged) return launch_batch_fn(batch_f_kernel<8, 16, K, ST, true, true>, t, 16, shmem, s);
+            return launch_batch_fn(batch_f_kernel<8, 16, K, ST, false, true>, t, 16, shmem, s);
+        }
+        if (t.ragged) return launch_batch_fn(batch_f_kernel<8, 16, K, ST, true, false>, t, 16, shmem, s);
+        return launch_batch_fn(batch_f_kernel<8, 16, K, ST, false, false>, t, 16, shmem, s);
     }
 #define MGK_CASE(C, W)                                                                  \
     if (cfg.cpt == C && cfg.nw == W) {                                                  \
@@ -672,17 +685,24 @@ static hipError_t launch_fn(Fn fn, const SweepArgs& a, int nw, size_t shmem, hip
     return hipGetLastError();
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
-static hipError_t launch_role(const SweepArgs& a, hipStream_t s)
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
+static hipError_t launch_role_f(const SweepArgs& a, hipStream_t s)
 {
     const size_t shmem = smem_bytes(CPT, NW);
     switch (a.end_mode) {
-    case END_NONE: return launch_fn(relax_f_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
-    case END_CSTEP: return launch_fn(relax_fc_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
-    case END_RESTRICT: return launch_fn(relax_fr_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
-    case END_PHI: return launch_fn(phi_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
+    case END_NONE: return launch_fn(relax_f_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
+    case END_CSTEP: return launch_fn(relax_fc_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
+    case END_RESTRICT: return launch_fn(relax_fr_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
+    case END_PHI: return launch_fn(phi_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG>
+static hipError_t launch_role(const SweepArgs& a, hipStream_t s)
+{
+    if (a.pc.roe) return launch_role_f<CPT, NW, K, ST, RAG, true>(a, s);
+    return launch_role_f<CPT, NW, K, ST, RAG, false>(a, s);
 }
 
 template <int CPT, int NW, int K, int ST>

@@ -150,7 +150,7 @@ __device__ __forceinline__ double load_agent(const double* p)
 //   [0] max |u^{+-}| over the tile, [1..3] Fa at the right faces of tile cells
 //   0, 1, 2, [4..6] Fb there, [7..9] Fa at the left faces of cells Tv-3,
 //   Tv-2, Tv-1, [10..12] Fb there.
-template <int CPT, int NW, int K, bool RAG>
+template <int CPT, int NW, int K, bool RAG, bool ROE = false>
 __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double (&A)[CPT], double& gA,
                                        const TGeo<CPT, NW>& g, const TSmem<CPT, NW>& sm, const PhiConst& pc,
                                        TSync& ts)
@@ -259,7 +259,7 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
         const double uL = (q == 0) ? uml : um[q - 1];
         double uR = (q == CPT) ? upr : up[q];
         if (RAG && q == g.nvalid) uR = upr;
-        if (pc.roe) {
+        if constexpr (ROE) {
             // the Roe flux needs no global coefficient: all of it in Fa
             Fa[q] = roe_flux2(uL, uR, pc.fa, pc.fb);
             Fb[q] = 0.0;
@@ -349,7 +349,7 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
             sm.misc[5 + lane] = load_agent(ts.slot(nb, parity) + idx);
         }
         if (lane == 0)
-            sm.misc[0] = pc.roe ? 0.0 : (pc.alpha_fixed > 0.0) ? pc.alpha_fixed : lf_alpha(mx, pc.fa, pc.fb);
+            sm.misc[0] = ROE ? 0.0 : (pc.alpha_fixed > 0.0) ? pc.alpha_fixed : lf_alpha(mx, pc.fa, pc.fb);
     }
     __syncthreads();
 
@@ -393,39 +393,39 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
 }
 
 // x <- Phi(x), ghost gx alongside (eq SSPRK1/2/3)
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __device__ __forceinline__ bool phi_t(double (&x)[CPT], double& gx, double dt, const TGeo<CPT, NW>& g,
                                       const TSmem<CPT, NW>& sm, const PhiConst& pc, TSync& ts)
 {
     double A[CPT], gA;
     if (ST == 1) {
-        if (!op_A_t<CPT, NW, K, RAG>(x, gx, A, gA, g, sm, pc, ts)) return false;
+        if (!op_A_t<CPT, NW, K, RAG, ROE>(x, gx, A, gA, g, sm, pc, ts)) return false;
 #pragma unroll
         for (int q = 0; q < CPT; ++q) x[q] = rk_first(x[q], A[q], dt);
         gx = rk_first(gx, gA, dt);
     } else if (ST == 2) {
         double v[CPT], gv;
-        if (!op_A_t<CPT, NW, K, RAG>(x, gx, A, gA, g, sm, pc, ts)) return false;
+        if (!op_A_t<CPT, NW, K, RAG, ROE>(x, gx, A, gA, g, sm, pc, ts)) return false;
 #pragma unroll
         for (int q = 0; q < CPT; ++q) v[q] = rk_first(x[q], A[q], dt);
         gv = rk_first(gx, gA, dt);
-        if (!op_A_t<CPT, NW, K, RAG>(v, gv, A, gA, g, sm, pc, ts)) return false;
+        if (!op_A_t<CPT, NW, K, RAG, ROE>(v, gv, A, gA, g, sm, pc, ts)) return false;
         const double hdt = 0.5 * dt;
 #pragma unroll
         for (int q = 0; q < CPT; ++q) x[q] = rk2_second(x[q], v[q], A[q], hdt);
         gx = rk2_second(gx, gv, gA, hdt);
     } else {
         double v[CPT], gv;
-        if (!op_A_t<CPT, NW, K, RAG>(x, gx, A, gA, g, sm, pc, ts)) return false;
+        if (!op_A_t<CPT, NW, K, RAG, ROE>(x, gx, A, gA, g, sm, pc, ts)) return false;
 #pragma unroll
         for (int q = 0; q < CPT; ++q) v[q] = rk_first(x[q], A[q], dt);
         gv = rk_first(gx, gA, dt);
-        if (!op_A_t<CPT, NW, K, RAG>(v, gv, A, gA, g, sm, pc, ts)) return false;
+        if (!op_A_t<CPT, NW, K, RAG, ROE>(v, gv, A, gA, g, sm, pc, ts)) return false;
         const double qdt = 0.25 * dt;
 #pragma unroll
         for (int q = 0; q < CPT; ++q) v[q] = rk3_second(x[q], v[q], A[q], qdt);
         gv = rk3_second(gx, gv, gA, qdt);
-        if (!op_A_t<CPT, NW, K, RAG>(v, gv, A, gA, g, sm, pc, ts)) return false;
+        if (!op_A_t<CPT, NW, K, RAG, ROE>(v, gv, A, gA, g, sm, pc, ts)) return false;
         const double tdt = (2.0 / 3.0) * dt;
 #pragma unroll
         for (int q = 0; q < CPT; ++q) x[q] = rk3_third(x[q], v[q], A[q], tdt);
@@ -492,7 +492,7 @@ __device__ __forceinline__ double t_sqdiff(const double (&a)[CPT], const double*
 }
 
 // One chunk on one tile: the same roles and storage as sweep_body.
-template <int CPT, int NW, int K, int ST, bool RAG, int END>
+template <int CPT, int NW, int K, int ST, bool RAG, int END, bool ROE>
 __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGeo<CPT, NW>& g,
                                             const TSmem<CPT, NW>& sm, TSync& ts)
 {
@@ -515,7 +515,7 @@ __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGe
 
     const int64_t n0 = (int64_t)c * a.m;
     for (int j = 1; j <= a.nsteps; ++j) {
-        if (!phi_t<CPT, NW, K, ST, RAG>(x, gx, a.dt, g, sm, a.pc, ts)) return false;
+        if (!phi_t<CPT, NW, K, ST, RAG, ROE>(x, gx, a.dt, g, sm, a.pc, ts)) return false;
         if (a.g != nullptr) t_add(x, gx, a.g + (n0 + j) * nx, g);
         if (a.fout != nullptr) {
             if (a.fout_every <= 1) t_store(x, a.fout + (n0 + j) * nx, g);
@@ -525,12 +525,12 @@ __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGe
 
     if constexpr (END == END_NONE) return true;
     if constexpr (END == END_PHI) {
-        if (!phi_t<CPT, NW, K, ST, RAG>(x, gx, a.dt, g, sm, a.pc, ts)) return false;
+        if (!phi_t<CPT, NW, K, ST, RAG, ROE>(x, gx, a.dt, g, sm, a.pc, ts)) return false;
         t_store(x, a.side_out + (int64_t)c * nx, g);
         return true;
     }
     const int64_t n1 = n0 + a.m;
-    if (!phi_t<CPT, NW, K, ST, RAG>(x, gx, a.dt, g, sm, a.pc, ts)) return false;
+    if (!phi_t<CPT, NW, K, ST, RAG, ROE>(x, gx, a.dt, g, sm, a.pc, ts)) return false;
     if (a.g != nullptr) t_add(x, gx, a.g + n1 * nx, g);
     const double* cnext = a.cref + (int64_t)(c + 1) * a.cref_stride * nx;
     if (a.resid_partial != nullptr) {
@@ -550,7 +550,7 @@ __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGe
     else t_store(x, a.uc_out + (int64_t)(c + 1) * nx, g);
     double y[CPT], gy;
     t_load(y, gy, cstart, g);
-    if (!phi_t<CPT, NW, K, ST, RAG>(y, gy, a.dt_next, g, sm, a.pc, ts)) return false;
+    if (!phi_t<CPT, NW, K, ST, RAG, ROE>(y, gy, a.dt_next, g, sm, a.pc, ts)) return false;
 #pragma unroll
     for (int q = 0; q < CPT; ++q) y[q] = x[q] - y[q];
     t_store(y, a.gc_out + (int64_t)(c + 1) * nx, g);
@@ -560,8 +560,8 @@ __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGe
 // Workgroup b: tile b % G of line group b / G; the group takes chunks
 // grp, grp + groups, ...  Every workgroup of a group runs the same sequence of
 // steps, hence the same sequence of synchronisations.
-template <int CPT, int NW, int K, int ST, bool RAG, int END>
-__device__ __forceinline__ void tiled_body(const SweepArgs& a)
+template <int CPT, int NW, int K, int ST, bool RAG, int END, bool ROE>
+__device__ __forceinline__ void tiled_body_t(const SweepArgs& a)
 {
     if (a.flag != nullptr && *a.flag != 0) return;
     extern __shared__ double smem_raw[];
@@ -580,31 +580,33 @@ __device__ __forceinline__ void tiled_body(const SweepArgs& a)
     ts.tile = tile;
     ts.ep = 0;
     for (int c = grp; c < a.nchunks; c += a.groups)
-        if (!tiled_chunk<CPT, NW, K, ST, RAG, END>(a, c, g, sm, ts)) return;
+        if (!tiled_chunk<CPT, NW, K, ST, RAG, END, ROE>(a, c, g, sm, ts)) return;
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
+// The four roles as separately named kernels; ROE (the numerical flux) is a
+// kernel parameter, so that each flux gets its own register allocation.
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __global__ __launch_bounds__(64 * NW) void tiled_relax_f_kernel(SweepArgs a)
 {
-    tiled_body<CPT, NW, K, ST, RAG, END_NONE>(a);
+    tiled_body_t<CPT, NW, K, ST, RAG, END_NONE, ROE>(a);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __global__ __launch_bounds__(64 * NW) void tiled_relax_fc_kernel(SweepArgs a)
 {
-    tiled_body<CPT, NW, K, ST, RAG, END_CSTEP>(a);
+    tiled_body_t<CPT, NW, K, ST, RAG, END_CSTEP, ROE>(a);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __global__ __launch_bounds__(64 * NW) void tiled_relax_fr_kernel(SweepArgs a)
 {
-    tiled_body<CPT, NW, K, ST, RAG, END_RESTRICT>(a);
+    tiled_body_t<CPT, NW, K, ST, RAG, END_RESTRICT, ROE>(a);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
 __global__ __launch_bounds__(64 * NW) void tiled_phi_kernel(SweepArgs a)
 {
-    tiled_body<CPT, NW, K, ST, RAG, END_PHI>(a);
+    tiled_body_t<CPT, NW, K, ST, RAG, END_PHI, ROE>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -635,17 +637,24 @@ static hipError_t launch_coop(Fn fn, const SweepArgs& a, int nw, size_t shmem, h
                                       (unsigned)shmem, s);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
-static hipError_t launch_tiled_role(const SweepArgs& a, hipStream_t s)
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
+static hipError_t launch_tiled_role_f(const SweepArgs& a, hipStream_t s)
 {
     const size_t shmem = tiled_smem_bytes(CPT, NW);
     switch (a.end_mode) {
-    case END_NONE: return launch_coop(tiled_relax_f_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
-    case END_CSTEP: return launch_coop(tiled_relax_fc_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
-    case END_RESTRICT: return launch_coop(tiled_relax_fr_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
-    case END_PHI: return launch_coop(tiled_phi_kernel<CPT, NW, K, ST, RAG>, a, NW, shmem, s);
+    case END_NONE: return launch_coop(tiled_relax_f_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
+    case END_CSTEP: return launch_coop(tiled_relax_fc_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
+    case END_RESTRICT: return launch_coop(tiled_relax_fr_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
+    case END_PHI: return launch_coop(tiled_phi_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG>
+static hipError_t launch_tiled_role(const SweepArgs& a, hipStream_t s)
+{
+    if (a.pc.roe) return launch_tiled_role_f<CPT, NW, K, ST, RAG, true>(a, s);
+    return launch_tiled_role_f<CPT, NW, K, ST, RAG, false>(a, s);
 }
 
 // The tile lengths (balanced, see TGeo) must lie in [3, 64 NW CPT]; the

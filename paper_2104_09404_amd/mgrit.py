@@ -27,7 +27,8 @@ EXPORTED = ["mgrit_phi", "mgrit_serial", "mgrit_relax", "mgrit_residual", "mgrit
             "mgrit_cycle", "mgrit_last_error", "mgrit_set_profiling", "mgrit_get_profile",
             "mgrit_kernel_config", "mgrit_set_kernel_config", "mgrit_phi_vjp", "mgrit_checkpoints",
             "mgrit_adjoint_workspace_bytes", "mgrit_adjoint", "mgrit_tiled_config", "mgrit_set_tiled_config",
-            "mgrit_batched_workspace_bytes", "mgrit_cycle_batched", "mgrit_cycle_levels"]
+            "mgrit_batched_workspace_bytes", "mgrit_cycle_batched", "mgrit_cycle_levels",
+            "mgrit_set_profiling_mask", "mgrit_autotune_scratch_bytes", "mgrit_autotune"]
 
 
 class MgritError(RuntimeError):
@@ -121,6 +122,12 @@ def load(path: str = LIB_PATH):
                                      vp]
     L.mgrit_last_error.restype = C.c_char_p
     L.mgrit_set_profiling.argtypes = [C.c_int]
+    L.mgrit_autotune_scratch_bytes.argtypes = [i32, i32]
+    L.mgrit_autotune_scratch_bytes.restype = C.c_size_t
+    L.mgrit_autotune.argtypes = [S, i32, i32, vp, C.c_size_t, i32, C.POINTER(i32), C.POINTER(i32),
+                                 C.POINTER(C.c_float), vp]
+    L.mgrit_set_profiling_mask.argtypes = [C.c_uint32]
+    L.mgrit_set_profiling_mask.restype = None
     L.mgrit_get_profile.argtypes = [C.POINTER(ProfileEntry), C.c_int]
     L.mgrit_kernel_config.argtypes = [i32, i32, C.POINTER(i32), C.POINTER(i32)]
     L.mgrit_set_kernel_config.argtypes = [i32, i32, i32, i32, i32]
@@ -135,7 +142,8 @@ def load(path: str = LIB_PATH):
     L.mgrit_cycle_batched.argtypes = [PR, i32, P, vp, C.c_size_t, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), vp]
     for name in EXPORTED:
-        if name in ("mgrit_last_error", "mgrit_set_profiling", "mgrit_workspace_bytes",
+        if name in ("mgrit_last_error", "mgrit_set_profiling", "mgrit_set_profiling_mask", "mgrit_workspace_bytes",
+                    "mgrit_autotune_scratch_bytes",
                     "mgrit_adjoint_workspace_bytes", "mgrit_batched_workspace_bytes"):
             continue
         getattr(L, name).restype = C.c_int
@@ -261,7 +269,41 @@ def cycle_levels(schemes, p: Params, u0, u, workspace=None, stream=None):
     return rc, [hist[i] for i in range(nres)], n
 
 
-def set_profiling(on: bool):
+def autotune(s: Scheme, nlines: int, nsteps: int = 8, install: bool = True, stream=None):
+    """Time every compiled one-workgroup launch shape for lines of s.nx cells
+    (nlines lines, nsteps steps of Phi) and return (cells_per_thread, waves,
+    ms) of the fastest; with ``install`` it becomes the override for that line
+    length in the regime of ``nlines``."""
+    import torch
+
+    n = load().mgrit_autotune_scratch_bytes(s.nx, nlines)
+    if n == 0:
+        raise MgritError(MGRIT_EINVAL, "nx and nlines must be positive")
+    scratch = torch.empty((n + 7) // 8, dtype=torch.float64, device="cuda")
+    cpt, nw, ms = C.c_int32(0), C.c_int32(0), C.c_float(0.0)
+    _check(load().mgrit_autotune(C.byref(s), nlines, nsteps, C.c_void_p(scratch.data_ptr()), n, 1 if install else 0,
+                                 C.byref(cpt), C.byref(nw), C.byref(ms), _stream(stream)))
+    return cpt.value, nw.value, ms.value
+
+
+def autotune_batch(problems, nsteps: int = 8, stream=None) -> dict:
+    """Tune the launch shape of every distinct (nx, k, stepper) of a batch of
+    (scheme, nt, dt, u0, u) problems in the throughput regime (a batch launch
+    holds many lines) and install the choices; returns {nx: (cpt, waves, ms)}."""
+    out = {}
+    for sch, nt, dt, u0, u in problems:
+        key = sch.nx
+        if key in out or sch.nx > 4096:
+            continue
+        out[key] = autotune(sch, 512, nsteps, install=True, stream=stream)
+    return out
+
+
+def set_profiling(on: bool, classes=None):
+    """Kernel timing on/off.  ``classes``: names from KERNEL_CLASSES whose
+    launches get HIP events (default: all); the others are counted only."""
+    mask = 0xFFFFFFFF if classes is None else sum(1 << KERNEL_CLASSES.index(c) for c in classes)
+    load().mgrit_set_profiling_mask(mask)
     load().mgrit_set_profiling(1 if on else 0)
 
 

@@ -8,6 +8,11 @@
         only the level-0 relaxation sweeps of the N_x = 1024 benchmark workload
         (mgrit_relax F-sweeps on the full level-0 array), for counter runs
         that should not include the rest of the cycle.
+    python -m paper_2104_09404_amd.profiling variants [reps]
+        the same level-0 F-sweep (512 chunks x 7 steps x 1024 cells, SSPRK3)
+        for every reconstruction degree k = 0..3 with the Lax-Friedrichs and
+        the Roe flux, each `reps` times in the order of VARIANTS, with its
+        time per sweep from HIP events on the launch stream.
 """
 from __future__ import annotations
 
@@ -42,11 +47,57 @@ def sweep(reps: int = 3):
     print("ran %d F-sweeps of %d chunks" % (reps, pb.nt // pb.m))
 
 
+# (k, numflux) in the order the variant sweeps run
+VARIANTS = [(0, 0), (1, 0), (2, 0), (3, 0), (0, 1), (1, 1), (2, 1), (3, 1)]
+
+
+def variant_name(k: int, numflux: int) -> str:
+    return "weno%d_%s" % (2 * k + 1, "roe" if numflux else "lf")
+
+
+def variants(reps: int = 5, quiet: bool = False) -> dict:
+    """Level-0 F-sweeps of the benchmark shape per scheme variant; returns
+    {name: {"ms_per_sweep", "cell_steps", "cell_steps_per_s"}} (median of
+    ``reps`` sweeps, each bracketed by HIP events on the current stream)."""
+    import numpy as np
+    import torch
+
+    from . import mgrit
+    from . import workloads as W
+
+    pb = W.w1_burgers_weno5()
+    base = np.tile(pb.u0, (pb.nt + 1, 1))
+    lvl = torch.from_numpy(base).cuda()
+    nchunks = pb.nt // pb.m
+    cell_steps = float(nchunks * (pb.m - 1) * pb.nx)
+    st = torch.cuda.current_stream()
+    out = {}
+    for k, numflux in VARIANTS:
+        s = mgrit.scheme(pb.nx, k=k, stepper=3, numflux=numflux)
+        mgrit.relax(s, pb.dt, pb.m, 0, lvl, None, pb.nt)  # warm-up
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            mgrit.relax(s, pb.dt, pb.m, 0, lvl, None, pb.nt)
+            e1.record(st)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        med = float(np.median(ms))
+        out[variant_name(k, numflux)] = {"ms_per_sweep": med, "cell_steps": cell_steps,
+                                         "cell_steps_per_s": cell_steps / (med * 1e-3)}
+        if not quiet:
+            print("%s %.4f ms per sweep" % (variant_name(k, numflux), med), flush=True)
+    return out
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "copy"
     if what == "copy":
         copy(int(sys.argv[2]) if len(sys.argv) > 2 else 256)
     elif what == "sweep":
         sweep(int(sys.argv[2]) if len(sys.argv) > 2 else 3)
+    elif what == "variants":
+        variants(int(sys.argv[2]) if len(sys.argv) > 2 else 5)
     else:
-        raise SystemExit("usage: python -m paper_2104_09404_amd.profiling copy|sweep [n]")
+        raise SystemExit("usage: python -m paper_2104_09404_amd.profiling copy|sweep|variants [n]")

@@ -175,3 +175,16 @@ def test_batch_validation_without_gpu(lib):
     st = (C.c_int32 * 2)()
     rc = lib.mgrit_cycle_batched(arr, 2, C.byref(p), None, 0, hist, its, st, None)
     assert rc == mgrit.MGRIT_EINVAL
+
+
+def test_autotune_validation_without_gpu(lib):
+    """The autotuner checks its arguments on the host: no scratch, or too
+    little, is an error before any device call."""
+    from paper_2104_09404_amd import mgrit
+
+    s = mgrit.scheme(1024)
+    assert lib.mgrit_autotune_scratch_bytes(1024, 512) >= 8 * 1024 * 512
+    assert lib.mgrit_autotune_scratch_bytes(4, 1) == 0
+    rc = lib.mgrit_autotune(C.byref(s), 512, 8, None, 0, 1, None, None, None, None)
+    assert rc == mgrit.MGRIT_EINVAL and b"scratch" in lib.mgrit_last_error()
+    assert lib.mgrit_autotune(C.byref(s), 0, 8, None, 0, 1, None, None, None, None) == mgrit.MGRIT_EINVAL
