@@ -130,37 +130,38 @@ MGK_HD void weno3_cell(double w0, double w1, double w2, double eps, double& um, 
 MGK_HD void weno7_cell(double w0, double w1, double w2, double w3, double w4, double w5, double w6, double eps,
                        double& um, double& up)
 {
+    // indicators, Horner-nested with explicit fused multiply-adds (the kernels
+    // are compiled without contraction)
+    const double b3 = fma(w0, fma(547.0, w0, fma(-3882.0, w1, fma(4642.0, w2, -1854.0 * w3))),
+                          fma(w1, fma(7043.0, w1, fma(-17246.0, w2, 7042.0 * w3)),
+                              fma(w2, fma(11003.0, w2, -9402.0 * w3), (2107.0 * w3) * w3)));
+    const double b2 = fma(w1, fma(267.0, w1, fma(-1642.0, w2, fma(1602.0, w3, -494.0 * w4))),
+                          fma(w2, fma(2843.0, w2, fma(-5966.0, w3, 1922.0 * w4)),
+                              fma(w3, fma(3443.0, w3, -2522.0 * w4), (547.0 * w4) * w4)));
+    const double b1 = fma(w2, fma(547.0, w2, fma(-2522.0, w3, fma(1922.0, w4, -494.0 * w5))),
+                          fma(w3, fma(3443.0, w3, fma(-5966.0, w4, 1602.0 * w5)),
+                              fma(w4, fma(2843.0, w4, -1642.0 * w5), (267.0 * w5) * w5)));
+    const double b0 = fma(w3, fma(2107.0, w3, fma(-9402.0, w4, fma(7042.0, w5, -1854.0 * w6))),
+                          fma(w4, fma(11003.0, w4, fma(-17246.0, w5, 4642.0 * w6)),
+                              fma(w5, fma(7043.0, w5, -3882.0 * w6), (547.0 * w6) * w6)));
     const double i240 = 1.0 / 240.0;
-    double b3 = w0 * (547.0 * w0 - 3882.0 * w1 + 4642.0 * w2 - 1854.0 * w3) +
-                w1 * (7043.0 * w1 - 17246.0 * w2 + 7042.0 * w3) + w2 * (11003.0 * w2 - 9402.0 * w3) +
-                2107.0 * w3 * w3;
-    double b2 = w1 * (267.0 * w1 - 1642.0 * w2 + 1602.0 * w3 - 494.0 * w4) +
-                w2 * (2843.0 * w2 - 5966.0 * w3 + 1922.0 * w4) + w3 * (3443.0 * w3 - 2522.0 * w4) +
-                547.0 * w4 * w4;
-    double b1 = w2 * (547.0 * w2 - 2522.0 * w3 + 1922.0 * w4 - 494.0 * w5) +
-                w3 * (3443.0 * w3 - 5966.0 * w4 + 1602.0 * w5) + w4 * (2843.0 * w4 - 1642.0 * w5) +
-                267.0 * w5 * w5;
-    double b0 = w3 * (2107.0 * w3 - 9402.0 * w4 + 7042.0 * w5 - 1854.0 * w6) +
-                w4 * (11003.0 * w4 - 17246.0 * w5 + 4642.0 * w6) + w5 * (7043.0 * w5 - 3882.0 * w6) +
-                547.0 * w6 * w6;
     double s0 = fma(b0, i240, eps), s1 = fma(b1, i240, eps), s2 = fma(b2, i240, eps), s3 = fma(b3, i240, eps);
     s0 *= s0;
     s1 *= s1;
     s2 *= s2;
     s3 *= s3;
     const double s01 = s0 * s1, s23 = s2 * s3;
-    const double P0 = s1 * s23, P1 = s0 * s23, P2 = s01 * s3, P3 = s01 * s2;  // prod of the other three
-    const double i12 = 1.0 / 12.0;
-    // u^-: candidate r with weight d_r on P_r
-    const double c0 = (3.0 * w3 + 13.0 * w4 - 5.0 * w5 + w6) * i12;
-    const double c1 = (-w2 + 7.0 * w3 + 7.0 * w4 - w5) * i12;
-    const double c2 = (w1 - 5.0 * w2 + 13.0 * w3 + 3.0 * w4) * i12;
-    const double c3 = (-3.0 * w0 + 13.0 * w1 - 23.0 * w2 + 25.0 * w3) * i12;
+    const double P0 = s1 * s23, P1 = s0 * s23, P2 = s01 * s3, P3 = s01 * s2;  // products of the other three
+    // u^-: candidate r (coefficients over 12) with weight d_r on P_r
+    const double c0 = fma(3.0 / 12.0, w3, fma(13.0 / 12.0, w4, fma(-5.0 / 12.0, w5, w6 * (1.0 / 12.0))));
+    const double c1 = fma(-1.0 / 12.0, w2, fma(7.0 / 12.0, w3, fma(7.0 / 12.0, w4, w5 * (-1.0 / 12.0))));
+    const double c2 = fma(1.0 / 12.0, w1, fma(-5.0 / 12.0, w2, fma(13.0 / 12.0, w3, w4 * (3.0 / 12.0))));
+    const double c3 = fma(-3.0 / 12.0, w0, fma(13.0 / 12.0, w1, fma(-23.0 / 12.0, w2, w3 * (25.0 / 12.0))));
     // u^+: mirror stencil r covers u^-'s stencil 3-r, weight d_r on P_{3-r}
-    const double e0 = (3.0 * w3 + 13.0 * w2 - 5.0 * w1 + w0) * i12;
-    const double e1 = (-w4 + 7.0 * w3 + 7.0 * w2 - w1) * i12;
-    const double e2 = (w5 - 5.0 * w4 + 13.0 * w3 + 3.0 * w2) * i12;
-    const double e3 = (-3.0 * w6 + 13.0 * w5 - 23.0 * w4 + 25.0 * w3) * i12;
+    const double e0 = fma(3.0 / 12.0, w3, fma(13.0 / 12.0, w2, fma(-5.0 / 12.0, w1, w0 * (1.0 / 12.0))));
+    const double e1 = fma(-1.0 / 12.0, w4, fma(7.0 / 12.0, w3, fma(7.0 / 12.0, w2, w1 * (-1.0 / 12.0))));
+    const double e2 = fma(1.0 / 12.0, w5, fma(-5.0 / 12.0, w4, fma(13.0 / 12.0, w3, w2 * (3.0 / 12.0))));
+    const double e3 = fma(-3.0 / 12.0, w6, fma(13.0 / 12.0, w5, fma(-23.0 / 12.0, w4, w3 * (25.0 / 12.0))));
     const double q0 = 4.0 * P0, q1 = 18.0 * P1, q2 = 12.0 * P2, q3 = P3;
     const double r0 = 4.0 * P3, r1 = 18.0 * P2, r2 = 12.0 * P1, r3 = P0;
     const double nm = fma(q0, c0, fma(q1, c1, fma(q2, c2, q3 * c3)));
