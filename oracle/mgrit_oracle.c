@@ -20,6 +20,8 @@
  *   WENO reconstruction of u^-_{i+1/2}, u^+_{i+1/2}      (sec 2.1.1, eq C, B, omega, D)
  *   Lax-Friedrichs flux with global alpha_LF             (sec 2.1.2, eq LFflux, eigs)
  *   Roe flux with the Harten-Hyman entropy fix           (sec 2.1.3, eq roeflux)
+ *   systems: shallow water and Euler, characteristic-    (sec 2, eq shallowWater, Euler;
+ *   wise reconstruction on the central cell's state        sec 2.1.1, 2.1.3)
  *   Phi = SSPRK3 / SSPRK2 / forward Euler                (sec 2.2, eq SSPRK3/2/1)
  *   MGRIT: F/FCF relaxation, FAS restriction, coarse     (sec 3.2, eq relaxation,
  *   solve, ideal interpolation, V- and F-cycles           restrictionOperator, FAScorrection,
@@ -57,6 +59,15 @@
  *       printed formula has no 1/2 on the sum and lambda/delta in q_H; with
  *       the 1/2 and lambda^2 it is the textbook scheme, which is upwind for
  *       Burgers (as printed it is not).
+ *   R18 Systems: alpha_k = l_k . (u+ - u-) with the LEFT eigenvectors l_k
+ *       (rows of R^{-1}) of the Roe matrix; the printed r_k would not give
+ *       the jump in the k-th characteristic variable.
+ *   R19 Euler Roe enthalpy: H_hat = (sqrt(rho+) H+ + sqrt(rho-) H-) /
+ *       (sqrt(rho+) + sqrt(rho-)) with H = (E + p)/rho; the printed weights
+ *       (E+p) sqrt(rho) break the Roe property f(u+) - f(u-) = A_hat (u+ - u-).
+ *   R20 Shallow water: g = 9.81 (the paper names g without a value; with
+ *       it the initial data of sec 4 give a coarsest CFL close to the 0.43
+ *       the paper quotes).
  */
 #include <math.h>
 #include <stdint.h>
@@ -68,12 +79,13 @@
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    int32_t flux;        /* 0: Burgers f(u) = u^2/2 (eq burgers); 1: linear advection f(u) = a u */
+    int32_t flux;        /* 0: Burgers f(u) = u^2/2 (eq burgers); 1: linear advection f(u) = a u; */
+                         /* 2: shallow water (D = 2, eq shallowWater); 3: Euler (D = 3, eq Euler) */
     int32_t k;           /* WENO polynomial degree k, order s = 2k+1: 0 (piecewise constant),    */
                          /* 1 (WENO3), 2 (WENO5), 3 (WENO7)                                      */
     int32_t stepper;     /* 1: forward Euler (eq SSPRK1), 2: SSPRK2, 3: SSPRK3                  */
     int32_t nx;          /* number of cells N_x                                                 */
-    double  a;           /* advection speed (flux == 1)                                          */
+    double  a;           /* flux parameter: advection speed (1), g (2), gamma (3)                */
     double  eps;         /* WENO epsilon (sec 2.1.1: usually 1e-6)                              */
     double  L;           /* domain length                                                        */
     double  alpha_fixed; /* > 0: use this value as alpha_LF instead of the global maximum       */
@@ -410,12 +422,257 @@ double orc_roe_flux(const orc_scheme* s, double um, double up)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Systems: shallow water (D = 2) and Euler (D = 3)                           */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * A line of a system holds its D components one after the other, each over
+ * the nx cells: u[d nx + i].  The flux parameter `a` is the gravitational
+ * constant g (shallow water) or the ratio of specific heats gamma (Euler).
+ */
+int orc_ncomp(const orc_scheme* s) { return s->flux == 2 ? 2 : (s->flux == 3 ? 3 : 1); }
+
+static int line_len(const orc_scheme* s) { return orc_ncomp(s) * s->nx; }
+
+/* f(u) of eq shallowWater / eq Euler (ideal gas, p = (gamma-1)(E - rho u^2/2)) */
+void orc_sys_flux(const orc_scheme* s, const double* u, double* f)
+{
+    if (s->flux == 2) {
+        double h = u[0], hu = u[1], v = hu / h, g = s->a;
+        f[0] = hu;
+        f[1] = hu * v + 0.5 * g * h * h;
+    } else {
+        double rho = u[0], m = u[1], E = u[2], v = m / rho, gam = s->a;
+        double p = (gam - 1.0) * (E - 0.5 * rho * v * v);
+        f[0] = m;
+        f[1] = m * v + p;
+        f[2] = (E + p) * v;
+    }
+}
+
+/* eigenvalues (ascending) and right eigenvectors (columns of R) of the flux
+   Jacobian for velocity v and, for shallow water, height h (c = sqrt(g h)),
+   for Euler, specific enthalpy H (c = sqrt((gamma-1)(H - v^2/2))) (sec 2.1.3) */
+static void eig_from(const orc_scheme* s, double v, double hH, double* lam, double R[3][3])
+{
+    memset(R, 0, sizeof(double) * 9);
+    if (s->flux == 2) {
+        double c = sqrt(s->a * hH);
+        lam[0] = v - c;
+        lam[1] = v + c;
+        R[0][0] = 1.0;
+        R[1][0] = lam[0];
+        R[0][1] = 1.0;
+        R[1][1] = lam[1];
+    } else {
+        double H = hH, c = sqrt((s->a - 1.0) * (H - 0.5 * v * v));
+        lam[0] = v - c;
+        lam[1] = v;
+        lam[2] = v + c;
+        R[0][0] = 1.0; R[1][0] = lam[0]; R[2][0] = H - v * c;
+        R[0][1] = 1.0; R[1][1] = v;      R[2][1] = 0.5 * v * v;
+        R[0][2] = 1.0; R[1][2] = lam[2]; R[2][2] = H + v * c;
+    }
+}
+
+/* L = R^{-1} (its rows are the left eigenvectors) */
+static void left_of(int D, double R[3][3], double L[3][3])
+{
+    long double a[9], inv[9];
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) a[i * D + j] = R[i][j];
+    mat_inverse(D, a, inv);
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) L[i][j] = (double)inv[i * D + j];
+}
+
+/* eigen-decomposition at the conserved state u */
+void orc_sys_eig(const orc_scheme* s, const double* u, double* lam, double* Rout, double* Lout)
+{
+    double R[3][3], L[3][3];
+    if (s->flux == 2) {
+        eig_from(s, u[1] / u[0], u[0], lam, R);
+    } else {
+        double rho = u[0], v = u[1] / rho, E = u[2];
+        double p = (s->a - 1.0) * (E - 0.5 * rho * v * v);
+        eig_from(s, v, (E + p) / rho, lam, R);
+    }
+    int D = orc_ncomp(s);
+    left_of(D, R, L);
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            Rout[i * D + j] = R[i][j];
+            Lout[i * D + j] = L[i][j];
+        }
+}
+
+/* eigen-decomposition at the Roe-averaged state of uL, uR (sec 2.1.3; reading R19) */
+void orc_sys_roe_eig(const orc_scheme* s, const double* uL, const double* uR, double* lam, double* Rout,
+                     double* Lout)
+{
+    double R[3][3], L[3][3];
+    if (s->flux == 2) {
+        double hL = uL[0], hR = uR[0], vL = uL[1] / hL, vR = uR[1] / hR;
+        double sL = sqrt(hL), sR = sqrt(hR);
+        double h_hat = (hR + hL) / 2.0;
+        double v_hat = (vR * sR + vL * sL) / (sR + sL);
+        eig_from(s, v_hat, h_hat, lam, R);
+    } else {
+        double rL = uL[0], rR = uR[0], vL = uL[1] / rL, vR = uR[1] / rR;
+        double pL = (s->a - 1.0) * (uL[2] - 0.5 * rL * vL * vL);
+        double pR = (s->a - 1.0) * (uR[2] - 0.5 * rR * vR * vR);
+        double HL = (uL[2] + pL) / rL, HR = (uR[2] + pR) / rR;
+        double sL = sqrt(rL), sR = sqrt(rR);
+        double v_hat = (vR * sR + vL * sL) / (sR + sL);
+        double H_hat = (HR * sR + HL * sL) / (sR + sL);
+        eig_from(s, v_hat, H_hat, lam, R);
+    }
+    int D = orc_ncomp(s);
+    left_of(D, R, L);
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            Rout[i * D + j] = R[i][j];
+            Lout[i * D + j] = L[i][j];
+        }
+}
+
+/* the Roe flux with the Harten-Hyman fix for a system (eq roeflux; readings R16, R18):
+   F = (f(uL) + f(uR))/2 - (1/2) sum_k q_H(lam_k) alpha_k r_k, alpha_k = l_k . (uR - uL) */
+void orc_sys_roe_flux(const orc_scheme* s, const double* uL, const double* uR, double* F)
+{
+    int D = orc_ncomp(s);
+    double fL[3], fR[3], lam[3], R[9], L[9], lamL[3], lamR[3], RL[9], LL[9];
+    orc_sys_flux(s, uL, fL);
+    orc_sys_flux(s, uR, fR);
+    orc_sys_roe_eig(s, uL, uR, lam, R, L);
+    orc_sys_eig(s, uL, lamL, RL, LL);
+    orc_sys_eig(s, uR, lamR, RL, LL);
+    for (int d = 0; d < D; ++d) F[d] = 0.5 * (fL[d] + fR[d]);
+    for (int k = 0; k < D; ++k) {
+        double alpha = 0.0;
+        for (int d = 0; d < D; ++d) alpha += L[k * D + d] * (uR[d] - uL[d]);
+        double delta = fmax(0.0, fmax(lam[k] - lamL[k], lamR[k] - lam[k]));
+        double qH;
+        if (fabs(lam[k]) < delta) qH = 0.5 * (lam[k] * lam[k] / delta + delta);
+        else qH = fabs(lam[k]);
+        for (int d = 0; d < D; ++d) F[d] -= 0.5 * qH * alpha * R[d * D + k];
+    }
+}
+
+/* characteristic-wise reconstruction in cell i (sec 2.1.1): the cells
+   i-k..i+k are decomposed on the eigenvectors of the central cell's state,
+   each characteristic variable is reconstructed as in the scalar case, and
+   the results are mapped back: um = u^-_{i+1/2}, up = u^+_{i-1/2} */
+static void sys_recon_cell(const orc_scheme* s, const double* u, int i, double* um, double* up)
+{
+    int D = orc_ncomp(s), n = s->nx, k = s->k;
+    if (k == 0) {
+        for (int d = 0; d < D; ++d) um[d] = up[d] = u[d * n + i];
+        return;
+    }
+    double ui[3], lam[3], R[9], L[9];
+    for (int d = 0; d < D; ++d) ui[d] = u[d * n + i];
+    orc_sys_eig(s, ui, lam, R, L);
+    double wm[3], wp[3];
+    for (int q = 0; q < D; ++q) {
+        double w[2 * ORC_KMAX + 1], wr[2 * ORC_KMAX + 1];
+        for (int j = 0; j <= 2 * k; ++j) {
+            int c = wrap(i - k + j, n);
+            double acc = 0.0;
+            for (int d = 0; d < D; ++d) acc += L[q * D + d] * u[d * n + c];
+            w[j] = acc;
+        }
+        for (int j = 0; j <= 2 * k; ++j) wr[j] = w[2 * k - j];
+        wm[q] = orc_weno_left(k, w, s->eps);
+        wp[q] = orc_weno_left(k, wr, s->eps);
+    }
+    for (int d = 0; d < D; ++d) {
+        double am = 0.0, ap = 0.0;
+        for (int q = 0; q < D; ++q) {
+            am += R[d * D + q] * wm[q];
+            ap += R[d * D + q] * wp[q];
+        }
+        um[d] = am;
+        up[d] = ap;
+    }
+}
+
+/* every cell's reconstructions: um[d nx + i] = u^-_{i+1/2}, up[d nx + i] = u^+_{i-1/2} */
+void orc_sys_recon(const orc_scheme* s, const double* u, double* um, double* up)
+{
+    int D = orc_ncomp(s), n = s->nx;
+    for (int i = 0; i < n; ++i) {
+        double a[3], b[3];
+        sys_recon_cell(s, u, i, a, b);
+        for (int d = 0; d < D; ++d) {
+            um[d * n + i] = a[d];
+            up[d * n + i] = b[d];
+        }
+    }
+}
+
+/* A(u) for a system (eq spaceDisc) with the LF flux (eq LFflux, eigs; reading R3,
+   R4: alpha_LF is the maximum of |lambda_k| over every interface, side and
+   wave) or the Roe flux; returns the alpha_LF used (0 with Roe) */
+static double sys_spatial_operator(const orc_scheme* s, const double* u, double* A)
+{
+    int D = orc_ncomp(s), n = s->nx;
+    double dx = s->L / (double)n;
+    double* um = (double*)malloc(sizeof(double) * (size_t)(D * n));
+    double* up = (double*)malloc(sizeof(double) * (size_t)(D * n));
+    double* F = (double*)malloc(sizeof(double) * (size_t)(D * n));
+    orc_sys_recon(s, u, um, up);
+    /* interface i+1/2: uL = u^- from cell i, uR = u^+ from cell i+1 */
+    double alpha = 0.0;
+    if (s->numflux == 0) {
+        if (s->alpha_fixed > 0.0) {
+            alpha = s->alpha_fixed;
+        } else {
+            for (int i = 0; i < n; ++i) {
+                double a[3], b[3], lam[3], R[9], L[9];
+                for (int d = 0; d < D; ++d) {
+                    a[d] = um[d * n + i];
+                    b[d] = up[d * n + wrap(i + 1, n)];
+                }
+                orc_sys_eig(s, a, lam, R, L);
+                for (int k = 0; k < D; ++k) alpha = fmax(alpha, fabs(lam[k]));
+                orc_sys_eig(s, b, lam, R, L);
+                for (int k = 0; k < D; ++k) alpha = fmax(alpha, fabs(lam[k]));
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double uL[3], uR[3], Fi[3];
+        for (int d = 0; d < D; ++d) {
+            uL[d] = um[d * n + i];
+            uR[d] = up[d * n + wrap(i + 1, n)];
+        }
+        if (s->numflux == 1) {
+            orc_sys_roe_flux(s, uL, uR, Fi);
+        } else {
+            double fL[3], fR[3];
+            orc_sys_flux(s, uL, fL);
+            orc_sys_flux(s, uR, fR);
+            for (int d = 0; d < D; ++d) Fi[d] = 0.5 * (fL[d] + fR[d]) - 0.5 * alpha * (uR[d] - uL[d]);
+        }
+        for (int d = 0; d < D; ++d) F[d * n + i] = Fi[d];
+    }
+    for (int d = 0; d < D; ++d)
+        for (int i = 0; i < n; ++i) A[d * n + i] = -(F[d * n + i] - F[d * n + wrap(i - 1, n)]) / dx;
+    free(um);
+    free(up);
+    free(F);
+    return alpha;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Semi-discrete operator A(u) (eq spaceDisc), LF or Roe flux                */
 /* ------------------------------------------------------------------------ */
 
 /* A[i] = -(F_{i+1/2} - F_{i-1/2})/dx.  Returns the alpha_LF used (0 with the Roe flux).  */
 double orc_spatial_operator(const orc_scheme* s, const double* u, double* A)
 {
+    if (s->flux >= 2) return sys_spatial_operator(s, u, A);
     int n = s->nx;
     double dx = s->L / (double)n;
     double* um = (double*)malloc(sizeof(double) * (size_t)n);
@@ -465,7 +722,7 @@ void orc_phi(const orc_scheme* s_in, double dt, const double* u, double* out)
     orc_scheme sc = *s_in;
     if (sc.lf_dx_dt) sc.alpha_fixed = (sc.L / (double)sc.nx) / dt;
     const orc_scheme* s = &sc;
-    int n = s->nx;
+    int n = line_len(s);
     size_t bytes = sizeof(double) * (size_t)n;
     double* u0 = (double*)malloc(bytes);
     double* A = (double*)malloc(bytes);
@@ -502,14 +759,14 @@ void orc_phi(const orc_scheme* s_in, double dt, const double* u, double* out)
 void orc_phi_lines(const orc_scheme* s, double dt, const double* u, double* out, int64_t nlines)
 {
     for (int64_t b = 0; b < nlines; ++b)
-        orc_phi(s, dt, u + b * s->nx, out + b * s->nx);
+        orc_phi(s, dt, u + b * line_len(s), out + b * line_len(s));
 }
 
 /* serial time stepping (forward block substitution of eq monolithicSystem):
    traj[0] = u0, traj[n+1] = Phi(traj[n]), n = 0..nt-1 */
 void orc_serial(const orc_scheme* s, double dt, int32_t nt, const double* u0, double* traj)
 {
-    int n = s->nx;
+    int n = line_len(s);
     memcpy(traj, u0, sizeof(double) * (size_t)n);
     for (int32_t t = 0; t < nt; ++t) orc_phi(s, dt, traj + (size_t)t * n, traj + (size_t)(t + 1) * n);
 }
@@ -605,7 +862,7 @@ static double* node(double* base, int n, int nx) { return base + (size_t)n * (si
 static void phi_level(orc_mg* mg, int l, const double* in, double* out)
 {
     const orc_scheme* s = mg->sl[l];
-    int nx = s->nx;
+    int nx = line_len(s);
     if (l >= 1 && mg->p->coarse_integrator != 0) {
         long M = 1;
         for (int j = 0; j < l; ++j) M *= mg->p->m;
@@ -625,7 +882,7 @@ static void phi_level(orc_mg* mg, int l, const double* in, double* out)
 /* dst = Phi_(l)(src) + g^n, with g^n taken as zero at level 0 for n >= 1 (eq monolithicSystem) */
 static void step_with_rhs(orc_mg* mg, int l, const double* src, int n, double* dst)
 {
-    int nx = mg->s->nx;
+    int nx = line_len(mg->s);
     phi_level(mg, l, src, mg->tmp);
     const double* gn = node(mg->g[l], n, nx);
     for (int i = 0; i < nx; ++i) dst[i] = mg->tmp[i] + gn[i];
@@ -634,7 +891,7 @@ static void step_with_rhs(orc_mg* mg, int l, const double* src, int n, double* d
 /* F-relaxation (eq relaxation): within every chunk, step from its C-point over its F-points */
 static void relax_F(orc_mg* mg, int l)
 {
-    int nx = mg->s->nx, m = mg->p->m, N = mg->nsteps[l];
+    int nx = line_len(mg->s), m = mg->p->m, N = mg->nsteps[l];
     for (int c = 0; c < N / m; ++c)
         for (int j = 1; j < m; ++j) {
             int n = c * m + j;
@@ -645,7 +902,7 @@ static void relax_F(orc_mg* mg, int l)
 /* C-relaxation: every C-point n = cm, c >= 1, from the preceding F-point */
 static void relax_C(orc_mg* mg, int l)
 {
-    int nx = mg->s->nx, m = mg->p->m, N = mg->nsteps[l];
+    int nx = line_len(mg->s), m = mg->p->m, N = mg->nsteps[l];
     for (int c = 1; c <= N / m; ++c) {
         int n = c * m;
         step_with_rhs(mg, l, node(mg->u[l], n - 1, nx), n, node(mg->u[l], n, nx));
@@ -655,7 +912,7 @@ static void relax_C(orc_mg* mg, int l)
 /* level-0 C-point residual of the current iterate (its F-points already relaxed), reading R10 */
 static double c_residual(orc_mg* mg)
 {
-    int nx = mg->s->nx, m = mg->p->m, N = mg->nsteps[0];
+    int nx = line_len(mg->s), m = mg->p->m, N = mg->nsteps[0];
     double sum = 0.0;
     for (int i = 1; i <= N / m; ++i) {
         step_with_rhs(mg, 0, node(mg->u[0], m * i - 1, nx), m * i, mg->tmp2);
@@ -673,7 +930,7 @@ static double c_residual(orc_mg* mg)
    restriction::u), reading R9 */
 static void restrict_fas(orc_mg* mg, int l)
 {
-    int nx = mg->s->nx, m = mg->p->m, Nc = mg->nsteps[l + 1];
+    int nx = line_len(mg->s), m = mg->p->m, Nc = mg->nsteps[l + 1];
     double* uf = mg->u[l];
     double* gf = mg->g[l];
     double* uc = mg->u[l + 1];
@@ -698,7 +955,7 @@ static void restrict_fas(orc_mg* mg, int l)
 /* coarsest-level solve (eq coarseCorr): forward substitution with Phi_(L-1) */
 static void coarse_solve(orc_mg* mg, int l)
 {
-    int nx = mg->s->nx, N = mg->nsteps[l];
+    int nx = line_len(mg->s), N = mg->nsteps[l];
     memcpy(node(mg->u[l], 0, nx), node(mg->g[l], 0, nx), sizeof(double) * (size_t)nx);
     for (int n = 1; n <= N; ++n)
         step_with_rhs(mg, l, node(mg->u[l], n - 1, nx), n, node(mg->u[l], n, nx));
@@ -708,7 +965,7 @@ static void coarse_solve(orc_mg* mg, int l)
    the C-points of level l, then F-relax level l */
 static void interpolate(orc_mg* mg, int l)
 {
-    int nx = mg->s->nx, m = mg->p->m, Nc = mg->nsteps[l + 1];
+    int nx = line_len(mg->s), m = mg->p->m, Nc = mg->nsteps[l + 1];
     for (int i = 0; i <= Nc; ++i)
         memcpy(node(mg->u[l], m * i, nx), node(mg->u[l + 1], i, nx), sizeof(double) * (size_t)nx);
     relax_F(mg, l);
@@ -776,7 +1033,7 @@ int orc_mgrit_levels(const orc_scheme* schemes, const orc_params* p, const doubl
     for (int l = 0; l < p->levels && l < 32; ++l) mg.sl[l] = &schemes[l];
     mg.p = p;
     mg.L = p->levels;
-    int nx = s->nx;
+    int nx = line_len(s);
     size_t line = (size_t)nx;
     int N = p->nt;
     for (int l = 0; l < mg.L; ++l) {

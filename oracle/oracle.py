@@ -98,6 +98,13 @@ def lib():
         L.orc_weno_left.restype = C.c_double
         L.orc_roe_flux.argtypes = [C.POINTER(Scheme), C.c_double, C.c_double]
         L.orc_roe_flux.restype = C.c_double
+        L.orc_ncomp.argtypes = [C.POINTER(Scheme)]
+        L.orc_ncomp.restype = C.c_int
+        L.orc_sys_flux.argtypes = [C.POINTER(Scheme), dp, dp]
+        L.orc_sys_eig.argtypes = [C.POINTER(Scheme), dp, dp, dp, dp]
+        L.orc_sys_roe_eig.argtypes = [C.POINTER(Scheme), dp, dp, dp, dp, dp]
+        L.orc_sys_roe_flux.argtypes = [C.POINTER(Scheme), dp, dp, dp]
+        L.orc_sys_recon.argtypes = [C.POINTER(Scheme), dp, dp, dp]
         L.orc_weno5_left_grad.argtypes = [dp, C.c_double, dp]
         L.orc_spatial_operator_vjp.argtypes = [C.POINTER(Scheme), dp, dp, dp]
         L.orc_phi_vjp.argtypes = [C.POINTER(Scheme), C.c_double, dp, dp, dp]
@@ -153,6 +160,66 @@ def weno5_left(v, eps=1e-6):
     return lib().orc_weno5_left(_p(v), eps)
 
 
+def shallow_water_scheme(nx, g=9.81, **kw) -> Scheme:
+    """Shallow water (D = 2, eq shallowWater); reading R20 for g."""
+    return scheme(nx, flux=2, a=g, **kw)
+
+
+def euler_scheme(nx, gamma=5.0 / 3.0, **kw) -> Scheme:
+    """Euler equations of an ideal monatomic gas (D = 3, eq Euler)."""
+    return scheme(nx, flux=3, a=gamma, **kw)
+
+
+def ncomp(s: Scheme) -> int:
+    return {2: 2, 3: 3}.get(s.flux, 1)
+
+
+def line_len(s: Scheme) -> int:
+    """Doubles per time node: the D components one after the other, nx each."""
+    return ncomp(s) * s.nx
+
+
+def sys_flux(s: Scheme, u):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    f = np.zeros(ncomp(s))
+    lib().orc_sys_flux(C.byref(s), _p(u), _p(f))
+    return f
+
+
+def sys_eig(s: Scheme, u):
+    """(eigenvalues, R, L = R^-1) of the flux Jacobian at the conserved state u."""
+    D = ncomp(s)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    lam, R, L = np.zeros(D), np.zeros((D, D)), np.zeros((D, D))
+    lib().orc_sys_eig(C.byref(s), _p(u), _p(lam), _p(R), _p(L))
+    return lam, R, L
+
+
+def sys_roe_eig(s: Scheme, uL, uR):
+    D = ncomp(s)
+    uL = np.ascontiguousarray(uL, dtype=np.float64)
+    uR = np.ascontiguousarray(uR, dtype=np.float64)
+    lam, R, L = np.zeros(D), np.zeros((D, D)), np.zeros((D, D))
+    lib().orc_sys_roe_eig(C.byref(s), _p(uL), _p(uR), _p(lam), _p(R), _p(L))
+    return lam, R, L
+
+
+def sys_roe_flux(s: Scheme, uL, uR):
+    uL = np.ascontiguousarray(uL, dtype=np.float64)
+    uR = np.ascontiguousarray(uR, dtype=np.float64)
+    F = np.zeros(ncomp(s))
+    lib().orc_sys_roe_flux(C.byref(s), _p(uL), _p(uR), _p(F))
+    return F
+
+
+def sys_recon(s: Scheme, u):
+    """(um, up) with um[d, i] = u^-_{i+1/2} and up[d, i] = u^+_{i-1/2} of cell i."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    um, up = np.zeros(u.size), np.zeros(u.size)
+    lib().orc_sys_recon(C.byref(s), _p(u), _p(um), _p(up))
+    return um.reshape(ncomp(s), s.nx), up.reshape(ncomp(s), s.nx)
+
+
 def weno_tables(k):
     """(c [k+1, k+1], d [k+1], B [k+1, k+1, k+1]) of degree k, computed from
     their definitions (eq C, B, D)."""
@@ -177,6 +244,7 @@ def roe_flux(s: Scheme, um, up):
 def spatial_operator(s: Scheme, u):
     u = np.ascontiguousarray(u, dtype=np.float64)
     A = np.zeros_like(u)
+    assert u.size == line_len(s)
     alpha = lib().orc_spatial_operator(C.byref(s), _p(u), _p(A))
     return A, alpha
 
@@ -185,7 +253,7 @@ def phi(s: Scheme, dt, u):
     """Phi applied to every row of ``u`` (shape [..., nx])."""
     u = np.ascontiguousarray(u, dtype=np.float64)
     out = np.zeros_like(u)
-    nlines = u.size // s.nx
+    nlines = u.size // line_len(s)
     lib().orc_phi_lines(C.byref(s), dt, _p(u), _p(out), nlines)
     return out
 
@@ -201,7 +269,7 @@ def psi(s: Scheme, order, M, dt, u):
 
 def serial(s: Scheme, dt, nt, u0):
     u0 = np.ascontiguousarray(u0, dtype=np.float64)
-    traj = np.zeros((nt + 1, s.nx))
+    traj = np.zeros((nt + 1, line_len(s)))
     lib().orc_serial(C.byref(s), dt, nt, _p(u0), _p(traj))
     return traj
 
@@ -209,7 +277,7 @@ def serial(s: Scheme, dt, nt, u0):
 def mgrit(s: Scheme, p: Params, u0, u_init=None):
     """Run FAS-MGRIT; returns (u [(nt+1) x nx], residual history, cycles applied, status)."""
     u0 = np.ascontiguousarray(u0, dtype=np.float64)
-    u = np.zeros((p.nt + 1, s.nx))
+    u = np.zeros((p.nt + 1, line_len(s)))
     if u_init is not None:
         u[...] = u_init
     hist = np.full(p.max_iter + 1, np.nan)
@@ -223,7 +291,7 @@ def mgrit_levels(schemes, p: Params, u0, u_init=None):
     """FAS-MGRIT with schemes[l] on level l; returns as :func:`mgrit`."""
     assert len(schemes) == p.levels
     arr = (Scheme * len(schemes))(*schemes)
-    nx = schemes[0].nx
+    nx = line_len(schemes[0])
     u0 = np.ascontiguousarray(u0, dtype=np.float64)
     u = np.zeros((p.nt + 1, nx))
     if u_init is not None:

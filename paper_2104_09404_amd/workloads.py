@@ -23,6 +23,9 @@ sizes of the five benchmark configurations:
 and the settings of the paper's own high-order experiment (Fig. MGRITweno):
 
   E4  e4_burgers_s{1,3,5,7}_{lf,roe}  N_x = 64, N_T = 400, 3-level V-cycle, m = 2
+      e4_{sw,euler}_s{1,3,5,7}_{lf,roe}  the same for shallow water and Euler
+
+A system's line holds its D components one after the other (D x N_x values).
 """
 from __future__ import annotations
 
@@ -36,6 +39,8 @@ SEED_BASE = 210409404
 
 FLUX_BURGERS = 0
 FLUX_ADVECTION = 1
+FLUX_SHALLOW_WATER = 2
+FLUX_EULER = 3
 
 
 @dataclasses.dataclass
@@ -43,7 +48,7 @@ class Problem:
     """One conservation-law problem plus its MGRIT settings."""
 
     name: str
-    flux: int              # 0 Burgers, 1 linear advection
+    flux: int              # 0 Burgers, 1 linear advection, 2 shallow water, 3 Euler
     k: int                 # WENO degree, order s = 2k+1 (0 first order, 2 WENO5)
     stepper: int           # 1 FE, 2 SSPRK2, 3 SSPRK3
     nx: int
@@ -53,7 +58,7 @@ class Problem:
     levels: int
     relax: int             # 0 F, 1 FCF
     u0: np.ndarray
-    a: float = 1.0
+    a: float = 1.0         # advection speed, g (shallow water) or gamma (Euler)
     eps: float = 1e-6
     L: float = 1.0
     tol: float = 1e-10
@@ -204,6 +209,24 @@ def e4_high_order(k: int = 2, numflux: int = 0, stepper: int = 3, max_iter: int 
     name = "e4_burgers_s%d_%s" % (2 * k + 1, "roe" if numflux else "lf")
     return Problem(name, FLUX_BURGERS, k, stepper, nx, nt, dt, 2, 3, 0, u0, max_iter=max_iter,
                    tol=-1.0, cfl=(4.0 / 3.0) * dt * nx, numflux=numflux)
+
+
+def e4_system(system: str, k: int = 2, numflux: int = 0, stepper: int = 3, max_iter: int = 20) -> Problem:
+    """Fig. MGRITweno for a system, settings as e4_high_order: shallow water
+    (g = 9.81) from h = (1 + sin(2 pi x)/2)/11, hu = 0; Euler (gamma = 5/3)
+    from rho = 1, rho u = 0, E = 1 + sin(2 pi x)/2 (exact cell averages)."""
+    nx, nt = 64, 400
+    sn = cell_average_sin(nx, 1, 0.0)
+    if system == "sw":
+        u0 = np.concatenate([(1.0 + 0.5 * sn) / 11.0, np.zeros(nx)])
+        flux, a, speed = FLUX_SHALLOW_WATER, 9.81, math.sqrt(9.81 * 1.5 / 11.0)
+    else:
+        u0 = np.concatenate([np.ones(nx), np.zeros(nx), 1.0 + 0.5 * sn])
+        flux, a, speed = FLUX_EULER, 5.0 / 3.0, math.sqrt(5.0 / 3.0 * (2.0 / 3.0) * 1.5)
+    dt = 0.5 / nt
+    name = "e4_%s_s%d_%s" % (system, 2 * k + 1, "roe" if numflux else "lf")
+    return Problem(name, flux, k, stepper, nx, nt, dt, 2, 3, 0, u0, a=a, max_iter=max_iter, tol=-1.0,
+                   cfl=speed * 4 * dt * nx, numflux=numflux)
 
 
 def random_lines(index: int, nlines: int, nx: int, mean: float = 0.5, amp: float = 0.3) -> np.ndarray:
