@@ -60,7 +60,22 @@ enum {
 /*
  * The fine propagator Phi (sec 2.1 - 2.2).
  *   flux     0: Burgers f(u) = u^2/2, lambda = u (eq burgers);
- *            1: linear advection f(u) = a u, lambda = a.
+ *            1: linear advection f(u) = a u, lambda = a;
+ *            2: shallow water (eq shallowWater), D = 2 components (h, hu),
+ *               gravitational constant a;
+ *            3: Euler (eq Euler), D = 3 components (rho, rho u, E), ideal gas
+ *               with ratio of specific heats a (the paper uses 5/3).
+ *            A system's time node is D x nx doubles, its components one after
+ *            the other (component d of cell i at d nx + i); every array of
+ *            the calls below then has D nx doubles per line or node.  Systems
+ *            reconstruct characteristic-wise on the eigenvectors of the
+ *            central cell's state (sec 2.1.1), take alpha_LF as the largest
+ *            |lambda_k| (eq eigs) and, with the Roe flux, Roe averages
+ *            (sec 2.1.3; u and H weighted by sqrt(h) or sqrt(rho)) and
+ *            alpha_k = l_k . (u+ - u-) with the left eigenvectors.  They run
+ *            on lines of at most 512 cells; batches, the adjoint, the
+ *            autotuner and fine-integrator matching cover scalar laws only
+ *            (MGRIT_EUNSUPPORTED / MGRIT_EINVAL).
  *   k        WENO polynomial degree (sec 2.1.1), order s = 2k+1: 0 = piecewise
  *            constant (u^-_{i+1/2} = u_i, u^+_{i+1/2} = u_{i+1}); 1 = WENO3;
  *            2 = WENO5-JS with the printed k = 2 tables; 3 = WENO7.  Stencil
@@ -70,7 +85,7 @@ enum {
  *            MGRIT_EUNSUPPORTED).
  *   stepper  1: forward Euler (eq SSPRK1); 2: SSPRK2; 3: SSPRK3 (eq SSPRK3).
  *   nx       number of cells N_x >= 8.
- *   a        advection speed (flux == 1).
+ *   a        flux parameter: advection speed (flux 1), g (flux 2), gamma (flux 3).
  *   eps      WENO epsilon of eq omega (> 0; the paper uses 1e-6).
  *   L        domain length (> 0); dx = L/nx.
  *   lf_dx_dt 1: the Lax-Friedrichs coefficient is dx/dt of the step being

@@ -83,6 +83,14 @@ bool cfg_compiled(int cpt, int nw)
 // fill the 256 compute units with one workgroup per line).
 const int kLatencyLines = 256;
 
+// systems (flux 2: shallow water, 3: Euler): D components per cell, one cell
+// per thread, lines of at most kMaxSysLine cells
+const int kMaxSysLine = 512;
+int ncomp(const mgrit_scheme* s) { return s->flux == 2 ? 2 : (s->flux == 3 ? 3 : 1); }
+bool is_system(const mgrit_scheme* s) { return s->flux >= 2; }
+// doubles per time node of the scheme's arrays
+int64_t line_len(const mgrit_scheme* s) { return (int64_t)ncomp(s) * s->nx; }
+
 bool choose_cfg_default(int nx, int nlines, KernelCfg* out);
 
 bool choose_cfg(int nx, int nlines, KernelCfg* out)
@@ -270,7 +278,9 @@ bool choose_tiled_adj(int nx, KernelCfg* out, int* tiles)
 int check_scheme(const mgrit_scheme* s)
 {
     if (s == nullptr) return fail(MGRIT_EINVAL, "scheme is NULL");
-    if (s->flux != 0 && s->flux != 1) return fail(MGRIT_EINVAL, "flux must be 0 (Burgers) or 1 (advection), got %d", s->flux);
+    if (s->flux < 0 || s->flux > 3)
+        return fail(MGRIT_EINVAL, "flux must be 0 (Burgers), 1 (advection), 2 (shallow water) or 3 (Euler), got %d",
+                    s->flux);
     if (s->k < 0 || s->k > 3) return fail(MGRIT_EINVAL, "k must be 0, 1, 2 or 3, got %d", s->k);
     if (s->stepper < 1 || s->stepper > 3) return fail(MGRIT_EINVAL, "stepper must be 1, 2 or 3, got %d", s->stepper);
     if (s->nx < 8) return fail(MGRIT_EINVAL, "nx must be >= 8, got %d", s->nx);
@@ -282,6 +292,15 @@ int check_scheme(const mgrit_scheme* s)
     if (s->numflux != 0 && s->numflux != 1) return fail(MGRIT_EINVAL, "numflux must be 0 (LF) or 1 (Roe), got %d", s->numflux);
     if (s->numflux == 1 && (s->alpha_fixed > 0.0 || s->lf_dx_dt != 0))
         return fail(MGRIT_EINVAL, "alpha_fixed and lf_dx_dt apply to the Lax-Friedrichs flux only");
+    if (is_system(s)) {
+        if (s->flux == 2 && !(s->a > 0.0 && std::isfinite(s->a)))
+            return fail(MGRIT_EINVAL, "shallow water: a is the gravitational constant and must be positive");
+        if (s->flux == 3 && !(s->a > 1.0 && std::isfinite(s->a)))
+            return fail(MGRIT_EINVAL, "Euler: a is the ratio of specific heats and must exceed 1");
+        if (s->nx > kMaxSysLine)
+            return fail(MGRIT_EUNSUPPORTED, "systems run on lines of at most %d cells, nx = %d", kMaxSysLine, s->nx);
+        return MGRIT_OK;
+    }
     KernelCfg c;
     int tiles = 0;
     const bool split = choose_tiled(s->nx, &c, &tiles);
@@ -296,6 +315,7 @@ int check_scheme(const mgrit_scheme* s)
 // the discrete adjoint covers the LF flux with k = 0 or 2
 int check_adjoint_scheme(const mgrit_scheme* s)
 {
+    if (is_system(s)) return fail(MGRIT_EUNSUPPORTED, "the adjoint covers scalar conservation laws only");
     if ((s->k != 0 && s->k != 2) || s->numflux != 0)
         return fail(MGRIT_EUNSUPPORTED, "the adjoint covers the Lax-Friedrichs flux with k = 0 or 2 (k = %d, numflux = %d)",
                     s->k, s->numflux);
@@ -331,7 +351,8 @@ SweepArgs base_args(const mgrit_scheme* s)
 {
     SweepArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.nx = s->nx;
+    a.nx = (int)line_len(s);
+    a.ncomp = ncomp(s);
     a.pc = phi_const(s);
     return a;
 }
@@ -413,6 +434,15 @@ int launch(int kc, const SweepArgs& a_in, const mgrit_scheme* s, hipStream_t st,
     KernelCfg cfg;
     int tiles = 0;
     SweepArgs a = a0;
+    if (is_system(s)) {
+        const int threads = ((s->nx + 63) / 64) * 64;
+        ProfLaunch pl;
+        int rc = pl.begin(kc, phi_lines, phi_lines * (double)s->nx, st);
+        if (rc) return rc;
+        hipError_t e = mgk::launch_sys(a, threads, s->flux, s->k, s->stepper, st);
+        if (e != hipSuccess) return hip_fail(e, "system sweep kernel launch");
+        return pl.end(st);
+    }
     const bool tiled = choose_tiled(s->nx, &cfg, &tiles);
     if (tiled && s->k == 3) return fail(MGRIT_EUNSUPPORTED, "WENO7 (k = 3) does not run on split lines");
     if (tiled && (a0.coarse_split || a0.gc_sub != nullptr))
@@ -522,7 +552,7 @@ int check_params(const mgrit_scheme* s, const mgrit_params* p)
     if (p->coarse_integrator < 0 || p->coarse_integrator > 2)
         return fail(MGRIT_EINVAL, "coarse_integrator must be 0, 1 or 2");
     if (p->coarse_integrator != 0) {
-        if (s->k != 0 || s->stepper != 1 || s->lf_dx_dt != 1)
+        if (s->k != 0 || s->stepper != 1 || s->lf_dx_dt != 1 || is_system(s))
             return fail(MGRIT_EINVAL, "fine-integrator matching needs the scheme of eq fineLF (k = 0, stepper 1, lf_dx_dt 1)");
         KernelCfg c;
         int t = 0;
@@ -546,7 +576,7 @@ Layout make_layout(const mgrit_scheme* s, const mgrit_params* p)
     Layout ly;
     std::memset(&ly, 0, sizeof(ly));
     ly.L = p->levels;
-    const size_t line = sizeof(double) * (size_t)s->nx;
+    const size_t line = sizeof(double) * (size_t)line_len(s);
     int N = p->nt;
     size_t off = 0;
     for (int l = 0; l < ly.L; ++l) {
@@ -562,7 +592,7 @@ Layout make_layout(const mgrit_scheme* s, const mgrit_params* p)
     const int nch0 = (ly.L > 1) ? p->nt / p->m : 1;
     KernelCfg tc;
     int tiles = 0;
-    ly.tiles = choose_tiled(s->nx, &tc, &tiles) ? tiles : 1;
+    ly.tiles = (!is_system(s) && choose_tiled(s->nx, &tc, &tiles)) ? tiles : 1;
     ly.side_off = off;
     off = align256(off + line * (size_t)(nch0 + 1));
     ly.partial_off = off;
@@ -825,6 +855,7 @@ int mgrit_autotune(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, void* 
 {
     int rc = check_scheme(s);
     if (rc) return rc;
+    if (is_system(s)) return fail(MGRIT_EUNSUPPORTED, "systems run one cell per thread: nothing to tune");
     if (nlines < 1 || nsteps < 1) return fail(MGRIT_EINVAL, "nlines and nsteps must be >= 1");
     if (scratch == nullptr || scratch_bytes < mgrit_autotune_scratch_bytes(s->nx, nlines))
         return fail(MGRIT_EINVAL, "scratch must hold nlines x nx doubles");
@@ -994,10 +1025,10 @@ int mgrit_relax(const mgrit_scheme* s, double dt, int32_t m, int32_t kind, doubl
         a.nsteps = 1;
         a.end_mode = mgk::END_NONE;
         a.dt = dt;
-        a.ustart = u + (size_t)(m - 1) * s->nx;
+        a.ustart = u + (size_t)(m - 1) * line_len(s);
         a.ustart_stride = m;
-        a.fout = u + (size_t)(m - 1) * s->nx;  // node c*m + 1 relative to the shifted base = (c+1) m
-        a.g = g ? g + (size_t)(m - 1) * s->nx : nullptr;
+        a.fout = u + (size_t)(m - 1) * line_len(s);  // node c*m + 1 relative to the shifted base = (c+1) m
+        a.g = g ? g + (size_t)(m - 1) * line_len(s) : nullptr;
         return launch(MGRIT_KC_RELAX_FC_C, a, s, st, (double)nch);
     };
     if (kind == 0) return F();
@@ -1023,7 +1054,7 @@ int mgrit_residual(const mgrit_scheme* s, double dt, int32_t m, const double* u,
     if (r == nullptr && u_coarse == nullptr) return MGRIT_OK;
     hipStream_t st = (hipStream_t)stream;
     const int nch = n / m;
-    const int64_t nx = s->nx;
+    const int64_t nx = line_len(s);
     // chunk c starts at its last F-point cm+m-1 and takes the step to C-point (c+1)m
     SweepArgs a = base_args(s);
     a.nchunks = nch;
@@ -1244,7 +1275,7 @@ static int run_cycle(const mgrit_scheme* const* sl, const mgrit_params* p, const
     cy.ws = (char*)workspace;
     cy.u0_level = u;
     cy.st = (hipStream_t)stream;
-    const int64_t nx = s->nx;
+    const int64_t nx = line_len(s);
     const int L = p->levels;
     cy.cstride0 = (p->storage == 0) ? (L > 1 ? p->m : 1) : 1;
     cy.fstore0 = p->storage == 0;
@@ -1375,13 +1406,13 @@ int mgrit_cycle_levels(const mgrit_scheme* schemes, const mgrit_params* p, const
     for (int l = 1; l < p->levels; ++l) {
         const mgrit_scheme* sl = &schemes[l];
         if ((rc = check_scheme(sl))) return rc;
-        if (sl->nx != s0->nx || sl->L != s0->L || sl->flux != s0->flux || (s0->flux == 1 && sl->a != s0->a))
+        if (sl->nx != s0->nx || sl->L != s0->L || sl->flux != s0->flux || (s0->flux >= 1 && sl->a != s0->a))
             return fail(MGRIT_EINVAL, "level %d: every level must have the same nx, L and conservation law", l);
         if (!same_scheme(&schemes[l - 1], sl)) mixed = true;
     }
     KernelCfg c;
     int tiles = 0;
-    if (mixed && choose_tiled(s0->nx, &c, &tiles))
+    if (mixed && !is_system(s0) && choose_tiled(s0->nx, &c, &tiles))
         return fail(MGRIT_EUNSUPPORTED, "a scheme per level runs on lines of one workgroup (at most %d cells)", kMaxLine);
     const mgrit_scheme* sl[16];
     for (int l = 0; l < 16; ++l) sl[l] = &schemes[l < p->levels ? l : p->levels - 1];
@@ -1447,6 +1478,8 @@ int check_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p
         const mgrit_problem& q = probs[i];
         int rc = check_scheme(&q.scheme);
         if (rc) return fail(rc, "problem %d: %s", i, mgrit_last_error());
+        if (is_system(&q.scheme))
+            return fail(MGRIT_EUNSUPPORTED, "problem %d: batches hold scalar conservation laws only", i);
         const mgrit_params pp = problem_params(p, &q);
         if ((rc = check_params(&q.scheme, &pp))) return fail(rc, "problem %d: %s", i, mgrit_last_error());
         if (q.scheme.k != probs[0].scheme.k || q.scheme.stepper != probs[0].scheme.stepper)

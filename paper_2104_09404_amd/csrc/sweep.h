@@ -69,7 +69,7 @@ struct SweepArgs {
     int psi_order;
     int psi_M;
     int psi_M_next;
-    int pad2_;
+    int ncomp;              // components per cell: 1, or D for a system (nx is then D x cells)
     double dt_fine;
     double alpha_next;      // > 0: LF coefficient of the coarse step of END_RESTRICT
     // lines split over several workgroups (tiled_impl.h)
@@ -230,6 +230,8 @@ hipError_t launch_tiled_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, i
                                 hipStream_t s);
 hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t nlines, hipStream_t s);
 hipError_t launch_fill_wave(double* u, int64_t nx, int64_t nlines, hipStream_t s);
+// systems (flux 2: shallow water, 3: Euler): one workgroup of `threads` per line
+hipError_t launch_sys(const SweepArgs& a, int threads, int flux, int k, int stepper, hipStream_t s);
 hipError_t launch_clear_ints(int* p, int n, hipStream_t s);
 hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_t s);
 hipError_t launch_reduce_norm(const double* partial, int n, double* hist, int* counter, int* flag, double tol,

@@ -184,6 +184,25 @@ def scheme(nx: int, flux: int = 0, k: int = 2, stepper: int = 3, a: float = 1.0,
                   lf_dx_dt=lf_dx_dt, numflux=numflux)
 
 
+def shallow_water_scheme(nx: int, g: float = 9.81, **kw) -> Scheme:
+    """Shallow water (flux 2, D = 2 components h, hu)."""
+    return scheme(nx, flux=2, a=g, **kw)
+
+
+def euler_scheme(nx: int, gamma: float = 5.0 / 3.0, **kw) -> Scheme:
+    """Euler equations of an ideal gas (flux 3, D = 3 components rho, rho u, E)."""
+    return scheme(nx, flux=3, a=gamma, **kw)
+
+
+def ncomp(s: Scheme) -> int:
+    return {2: 2, 3: 3}.get(s.flux, 1)
+
+
+def line_len(s: Scheme) -> int:
+    """Doubles per line or time node: the D components one after the other."""
+    return ncomp(s) * s.nx
+
+
 def fine_lf_scheme(nx: int, flux: int = 0, a: float = 1.0, L: float = 1.0) -> Scheme:
     """The scheme of eq fineLF: first order, forward Euler, alpha_LF = dx/dt."""
     return scheme(nx, flux=flux, k=0, stepper=1, a=a, L=L, lf_dx_dt=1)
@@ -206,7 +225,7 @@ def scheme_from_problem(pb) -> Scheme:
 
 def phi(s: Scheme, dt: float, u_in, u_out, stream=None):
     """u_out[b] = Phi(u_in[b]) for every line b."""
-    nlines = u_in.numel() // s.nx
+    nlines = u_in.numel() // line_len(s)
     _check(load().mgrit_phi(C.byref(s), dt, _ptr(u_in), _ptr(u_out), nlines, _stream(stream)))
 
 

@@ -188,3 +188,19 @@ def test_autotune_validation_without_gpu(lib):
     rc = lib.mgrit_autotune(C.byref(s), 512, 8, None, 0, 1, None, None, None, None)
     assert rc == mgrit.MGRIT_EINVAL and b"scratch" in lib.mgrit_last_error()
     assert lib.mgrit_autotune(C.byref(s), 0, 8, None, 0, 1, None, None, None, None) == mgrit.MGRIT_EINVAL
+
+
+def test_system_validation_without_gpu(lib):
+    """Systems: the flux parameter is checked (g > 0, gamma > 1), lines are
+    limited to 512 cells, and the cycle workspace holds D x nx doubles per
+    node."""
+    from paper_2104_09404_amd import mgrit
+
+    assert lib.mgrit_phi(C.byref(mgrit.shallow_water_scheme(64, g=0.0)), 1e-3, None, None, 1, None) == mgrit.MGRIT_EINVAL
+    assert lib.mgrit_phi(C.byref(mgrit.euler_scheme(64, gamma=1.0)), 1e-3, None, None, 1, None) == mgrit.MGRIT_EINVAL
+    assert lib.mgrit_phi(C.byref(mgrit.euler_scheme(513)), 1e-3, None, None, 1, None) == mgrit.MGRIT_EUNSUPPORTED
+    assert lib.mgrit_phi(C.byref(mgrit.scheme(64, flux=4)), 1e-3, None, None, 1, None) == mgrit.MGRIT_EINVAL
+    p = mgrit.params(512, 1e-3, 8, 2)
+    n1 = lib.mgrit_workspace_bytes(C.byref(mgrit.scheme(64)), C.byref(p))
+    n3 = lib.mgrit_workspace_bytes(C.byref(mgrit.euler_scheme(64)), C.byref(p))
+    assert n3 > 2.5 * n1
