@@ -92,6 +92,41 @@ def variant_rates():
             "kernel": "relax_f_kernel<4, 4, k, 3, false, roe>", "variants": rates}
 
 
+def measured_system_flops():
+    """Executed FP64 flops per cell-step of the system sweeps from
+    profiles/system_flops.json, or None when missing or stale (as for the
+    scheme variants)."""
+    import hashlib
+
+    try:
+        with open(os.path.join(ROOT, "profiles", "system_flops.json")) as f:
+            rec = json.load(f)
+        h = hashlib.sha256()
+        for name in rec["sources"]:
+            with open(os.path.join(ROOT, name), "rb") as f:
+                h.update(f.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["flops_per_cell_step"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
+def system_rates():
+    """Row f4 measured: F-sweeps of 512 chunks x 7 SSPRK3 steps on 512-cell
+    lines of shallow water and Euler."""
+    from paper_2104_09404_amd import profiling
+
+    rates = profiling.systems(reps=5, quiet=True)
+    flops = measured_system_flops()
+    for name, r in rates.items():
+        f = flops.get(name) if flops else None
+        r["executed_flops_per_cell_step"] = f
+        r["tflops"] = f * r["cell_steps_per_s"] / 1e12 if f else None
+        r["frac_fp64_peak"] = f * r["cell_steps_per_s"] / PEAK_FP64 if f else None
+    return {"workload": "F-sweep of 512 chunks x 7 SSPRK3 steps on 512-cell lines (shallow water g = 9.81, "
+                        "Euler gamma = 5/3), CFL 0.4",
+            "kernel": "sys_relax_f_kernel<D, k, 3, roe>", "systems": rates}
+
+
 def time_to_tolerance(mgrit):
     """MGRIT wall time to a residual of 1e-10 where MGRIT converges (the
     benchmark workload's coarse CFL of 51 makes it diverge, as the paper
@@ -145,7 +180,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the reference-oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="skip the scheme-variant sweeps")
+    ap.add_argument("--no-variants", action="store_true", help="skip the scheme-variant and system sweeps")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward ratio (its split-line launches are cooperative)")
     return ap.parse_args()
@@ -321,6 +356,7 @@ def main():
         "gpu_serial_ms": gpu_serial_ms(mgrit, s, pb, u0),
         "time_to_tolerance": time_to_tolerance(mgrit),
         "scheme_variants": None if args.no_variants else variant_rates(),
+        "systems": None if args.no_variants else system_rates(),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb, args.cpu_seconds)

@@ -13,6 +13,10 @@
         for every reconstruction degree k = 0..3 with the Lax-Friedrichs and
         the Roe flux, each `reps` times in the order of VARIANTS, with its
         time per sweep from HIP events on the launch stream.
+    python -m paper_2104_09404_amd.profiling systems [reps]
+        the same shape of F-sweep (512 chunks x 7 SSPRK3 steps) for shallow
+        water and Euler on 512-cell lines, WENO degrees 0, 2 and 3, LF and Roe,
+        in the order of SYSTEMS.
 """
 from __future__ import annotations
 
@@ -91,6 +95,59 @@ def variants(reps: int = 5, quiet: bool = False) -> dict:
     return out
 
 
+# (system, k, numflux) in the order the system sweeps run
+SYSTEMS = [(sysname, k, numflux) for sysname in ("sw", "euler") for k in (0, 2, 3) for numflux in (0, 1)]
+
+
+def system_name(sysname: str, k: int, numflux: int) -> str:
+    return "%s_weno%d_%s" % (sysname, 2 * k + 1, "roe" if numflux else "lf")
+
+
+def systems(reps: int = 5, quiet: bool = False) -> dict:
+    """Level-0 F-sweeps of 512 chunks x 7 steps on 512-cell lines of shallow
+    water (h = 1 + sin(2 pi x)/4, hu = 0) and Euler (rho = 1, rho u = 0,
+    E = 1 + sin(2 pi x)/4) at CFL 0.4; returns {name: {"ms_per_sweep",
+    "cell_steps", "cell_steps_per_s"}} (median of ``reps``, HIP events)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from . import mgrit
+    from . import workloads as W
+
+    nx, m, nt = 512, 8, 4096
+    sn = W.cell_average_sin(nx, 1, 0.0)
+    init = {"sw": (np.concatenate([1.0 + 0.25 * sn, np.zeros(nx)]), math.sqrt(9.81 * 1.25)),
+            "euler": (np.concatenate([np.ones(nx), np.zeros(nx), 1.0 + 0.25 * sn]),
+                      math.sqrt(5.0 / 3.0 * (2.0 / 3.0) * 1.25))}
+    cell_steps = float((nt // m) * (m - 1) * nx)
+    st = torch.cuda.current_stream()
+    out = {}
+    for sysname, k, numflux in SYSTEMS:
+        u0, speed = init[sysname]
+        lvl = torch.from_numpy(np.tile(u0, (nt + 1, 1))).cuda()
+        s = (mgrit.shallow_water_scheme(nx, k=k, numflux=numflux) if sysname == "sw"
+             else mgrit.euler_scheme(nx, k=k, numflux=numflux))
+        dt = 0.4 / nx / speed
+        mgrit.relax(s, dt, m, 0, lvl, None, nt)  # warm-up
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            mgrit.relax(s, dt, m, 0, lvl, None, nt)
+            e1.record(st)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        med = float(np.median(ms))
+        name = system_name(sysname, k, numflux)
+        out[name] = {"ms_per_sweep": med, "cell_steps": cell_steps, "cell_steps_per_s": cell_steps / (med * 1e-3)}
+        if not quiet:
+            print("%s %.4f ms per sweep" % (name, med), flush=True)
+        del lvl
+    return out
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "copy"
     if what == "copy":
@@ -99,5 +156,7 @@ if __name__ == "__main__":
         sweep(int(sys.argv[2]) if len(sys.argv) > 2 else 3)
     elif what == "variants":
         variants(int(sys.argv[2]) if len(sys.argv) > 2 else 5)
+    elif what == "systems":
+        systems(int(sys.argv[2]) if len(sys.argv) > 2 else 5)
     else:
-        raise SystemExit("usage: python -m paper_2104_09404_amd.profiling copy|sweep|variants [n]")
+        raise SystemExit("usage: python -m paper_2104_09404_amd.profiling copy|sweep|variants|systems [n]")
