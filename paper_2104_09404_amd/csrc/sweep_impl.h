@@ -385,19 +385,56 @@ __device__ __forceinline__ void level_step(double (&x)[CPT], double dt, int M, c
     phi<CPT, NW, K, ST, RAG, ROE>(x, dt, g, sm, pc, par);
 }
 
-template <int CPT, int NW>
-__device__ __forceinline__ void load_line(double (&x)[CPT], const double* src, const Geo<CPT, NW>& g)
+// Reads the thread's cells of a line into t without using them, so that the
+// loads stay in flight until the values are needed.  Every lane reads in
+// bounds and without a branch: a lane that owns no cell reads the line's
+// first cells, and (RAG) the ragged lane its last cell in place of the
+// missing ones; without RAG every active lane owns CPT cells and the line
+// holds at least CPT.  (A load under its own per-cell predicate would be
+// waited for before the next one is issued: one memory round trip per cell.)
+// Only t[q] with q < nvalid is meaningful.
+template <int CPT, int NW, bool RAG = true>
+__device__ __forceinline__ void fetch_line(double (&t)[CPT], const double* src, const Geo<CPT, NW>& g)
 {
-    if (g.active) {
+    // 32-bit cell indices off the (wave-uniform) line pointer
+    const int j0 = g.active ? g.j0 : 0;
+    if constexpr (RAG) {
+        const int last = g.active ? g.nvalid - 1 : 0;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q)
-            if (q < g.nvalid) x[q] = src[g.j0 + q];
-            else x[q] = 0.0;
+        for (int q = 0; q < CPT; ++q) t[q] = src[j0 + (q < last ? q : last)];
     } else {
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) x[q] = 0.0;
+        for (int q = 0; q < CPT; ++q) t[q] = src[j0 + q];
     }
 }
+
+// The thread's cells of a line, 0 where it owns none.
+template <int CPT, int NW, bool RAG = true>
+__device__ __forceinline__ void load_line(double (&x)[CPT], const double* src, const Geo<CPT, NW>& g)
+{
+    double t[CPT];
+    fetch_line<CPT, NW, RAG>(t, src, g);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) x[q] = (q < g.nvalid) ? t[q] : 0.0;
+}
+
+// Waits for every outstanding vector memory operation of the thread (loads
+// and stores).  Placed before a step loop where loads or stores are pending:
+// the compiler otherwise carries them into the loop's entry and waits at the
+// top of every step, which then also waits for the previous step's stores.
+__device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// How a step loop gets the right-hand side g of each step, as a compile-time
+// tag for a generic lambda (one compiled loop per mode):
+//   RHS_NONE:  no right-hand side (level 0);
+//   RHS_AHEAD: g of the next step is read while the current one runs;
+//   RHS_LATE:  g is read after the step's stages, if there is one (run-time
+//              test; for kernels whose registers cannot hold g across stages).
+enum RhsMode { RHS_NONE = 0, RHS_AHEAD = 1, RHS_LATE = 2 };
+template <int M>
+struct RhsTag {
+    static constexpr int value = M;
+};
 
 template <int CPT, int NW>
 __device__ __forceinline__ void store_line(const double (&x)[CPT], double* dst, const Geo<CPT, NW>& g)
@@ -409,37 +446,41 @@ __device__ __forceinline__ void store_line(const double (&x)[CPT], double* dst, 
     }
 }
 
-template <int CPT, int NW>
-__device__ __forceinline__ void add_line(double (&x)[CPT], const double* src, const Geo<CPT, NW>& g)
+// x += t on every cell slot of the thread.  The slots it does not own (past
+// the line end) carry values that no owned cell's arithmetic reads: the
+// stage code takes those window positions from the wrapped line in LDS and
+// leaves inactive lanes out of the alpha reduction, and stores skip them.
+// Without a per-cell select the stored registers are x itself, not
+// temporaries that the next step would reuse while the stores are pending
+// (which would make it wait for them).
+template <int CPT>
+__device__ __forceinline__ void add_line(double (&x)[CPT], const double (&t)[CPT])
 {
-    if (g.active) {
 #pragma unroll
-        for (int q = 0; q < CPT; ++q)
-            if (q < g.nvalid) x[q] = x[q] + src[g.j0 + q];
-    }
+    for (int q = 0; q < CPT; ++q) x[q] = x[q] + t[q];
 }
 
-template <int CPT, int NW>
+template <int CPT, int NW, bool RAG = true>
 __device__ __forceinline__ void copy_line(const double* src, double* dst, const Geo<CPT, NW>& g)
 {
-    if (g.active) {
-#pragma unroll
-        for (int q = 0; q < CPT; ++q)
-            if (q < g.nvalid) dst[g.j0 + q] = src[g.j0 + q];
-    }
+    double t[CPT];
+    fetch_line<CPT, NW, RAG>(t, src, g);
+    store_line(t, dst, g);
 }
 
 // sum of squares of (a - b) over the line, in a fixed order; valid in thread 0
-template <int CPT, int NW>
+template <int CPT, int NW, bool RAG = true>
 __device__ __forceinline__ double line_sqdiff(const double (&a)[CPT], const double* b, const Geo<CPT, NW>& g,
                                               const Smem<CPT, NW>& sm)
 {
     double s = 0.0;
     if (g.active) {
+        double t[CPT];
+        fetch_line<CPT, NW, RAG>(t, b, g);
 #pragma unroll
         for (int q = 0; q < CPT; ++q)
             if (q < g.nvalid) {
-                const double d = a[q] - b[g.j0 + q];
+                const double d = a[q] - t[q];
                 s = fma(d, d, s);
             }
     }
@@ -470,30 +511,77 @@ __device__ __forceinline__ void sweep_body_t(const SweepArgs& a, const int c)
     const double* src = (a.side_in != nullptr && c > 0) ? a.side_in + (int64_t)c * nx
                                                         : a.ustart + (int64_t)c * a.ustart_stride * nx;
     double x[CPT];
-    load_line(x, src, g);
+    load_line<CPT, NW, RAG>(x, src, g);
+    wait_loads();
     if (a.ucommit != nullptr) store_line(x, a.ucommit + (int64_t)c * a.ucommit_stride * nx, g);
     if (a.inject_last && c == a.nchunks - 1) {
         // the level's final C-point is committed / injected as well
         const double* last = (a.side_in != nullptr) ? a.side_in + (int64_t)a.nchunks * nx
                                                     : a.ustart + (int64_t)a.nchunks * a.ustart_stride * nx;
-        copy_line(last, a.ucommit + (int64_t)a.nchunks * a.ucommit_stride * nx, g);
+        copy_line<CPT, NW, RAG>(last, a.ucommit + (int64_t)a.nchunks * a.ucommit_stride * nx, g);
+        // (the copies' registers are reused in the step loop, which would
+        // otherwise wait at every step for these stores)
+        wait_loads();
     }
     // the chunk's starting C-point (the source of the coarse step of END_RESTRICT)
     const double* cstart = (a.ystart != nullptr) ? a.ystart + (int64_t)c * a.ystart_stride * nx : src;
     if (END == END_RESTRICT && c == 0) {
         // coarse node 0: u_c^0 = u^0, g_c^0 = g^0 (= u^0 at level 0)
-        copy_line(cstart, a.uc_out, g);
-        copy_line(a.g != nullptr ? a.g : cstart, a.gc_out, g);
+        copy_line<CPT, NW, RAG>(cstart, a.uc_out, g);
+        copy_line<CPT, NW, RAG>(a.g != nullptr ? a.g : cstart, a.gc_out, g);
+        wait_loads();
     }
 
+    // Step j of the loop ends at node n0 + j; the C-step after it (END_CSTEP,
+    // END_RESTRICT) at n1 = n0 + m.  With up to 4 cells per thread the
+    // right-hand side of the next step is read one step ahead, so that its
+    // loads are in flight during the stages, and the loop is compiled once
+    // with and once without a right-hand side (level 0 has none), so that
+    // neither version carries the other's loads, adds or waits.  With 8 cells
+    // per thread the registers that would hold g across the stages cost more
+    // than the wait, and one loop reads g after each step's stages.
+    constexpr bool AHEAD = CPT <= 4;
     const int64_t n0 = (int64_t)c * a.m;
-    for (int j = 1; j <= a.nsteps; ++j) {
-        level_step<CPT, NW, K, ST, RAG, ROE>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
-        if (a.g != nullptr) add_line(x, a.g + (n0 + j) * nx, g);
-        if (a.fout != nullptr) {
-            if (a.fout_every <= 1) store_line(x, a.fout + (n0 + j) * nx, g);
-            else if ((n0 + j) % a.fout_every == 0) store_line(x, a.fout + ((n0 + j) / a.fout_every) * nx, g);
+    const int64_t n1 = n0 + a.m;
+    constexpr bool cend = (END == END_CSTEP || END == END_RESTRICT);
+    const int nrhs = a.nsteps + (cend ? 1 : 0);
+    const bool hg = a.g != nullptr;
+    auto rhs_node = [&](int j) -> int64_t { return j <= a.nsteps ? n0 + j : n1; };
+    double gn[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) gn[q] = 0.0;
+    if (AHEAD && hg && nrhs >= 1) fetch_line<CPT, NW, RAG>(gn, a.g + rhs_node(1) * nx, g);
+    auto steps = [&](auto mode) {
+        constexpr int M = decltype(mode)::value;
+        // strided trajectory: position of node n0 + j among the stored nodes
+        const int every = a.fout_every > 1 ? a.fout_every : 1;
+        int frem = (int)((n0 + 1) % every);
+        int64_t fidx = (n0 + 1) / every;
+        for (int j = 1; j <= a.nsteps; ++j) {
+            level_step<CPT, NW, K, ST, RAG, ROE>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
+            if constexpr (M == RHS_AHEAD) {
+                add_line(x, gn);
+            } else if constexpr (M == RHS_LATE) {
+                if (hg) {
+                    fetch_line<CPT, NW, RAG>(gn, a.g + rhs_node(j) * nx, g);
+                    add_line(x, gn);
+                }
+            }
+            if (a.fout != nullptr && frem == 0) store_line(x, a.fout + fidx * nx, g);
+            if constexpr (M == RHS_AHEAD) {
+                if (j < nrhs) fetch_line<CPT, NW, RAG>(gn, a.g + rhs_node(j + 1) * nx, g);
+            }
+            if (++frem == every) {
+                frem = 0;
+                ++fidx;
+            }
         }
+    };
+    if constexpr (AHEAD) {
+        if (hg) steps(RhsTag<RHS_AHEAD>{});
+        else steps(RhsTag<RHS_NONE>{});
+    } else {
+        steps(RhsTag<RHS_LATE>{});
     }
 
     if constexpr (END == END_NONE) return;
@@ -502,44 +590,50 @@ __device__ __forceinline__ void sweep_body_t(const SweepArgs& a, const int c)
         if (a.gc_sub != nullptr) {
             // the second half of a split FAS restriction: g_c = t - Phi_{l+1}(chunk start)
             double* out = a.gc_sub + (int64_t)(c + 1) * nx;
+            double t[CPT];
+            fetch_line<CPT, NW, RAG>(t, out, g);
             if (g.active) {
 #pragma unroll
                 for (int q = 0; q < CPT; ++q)
-                    if (q < g.nvalid) out[g.j0 + q] = out[g.j0 + q] - x[q];
+                    if (q < g.nvalid) out[g.j0 + q] = t[q] - x[q];
             }
             return;
         }
         store_line(x, a.side_out + (int64_t)c * nx, g);
         return;
     }
-    // one more step to the chunk's end C-point n1 = (c+1) m
-    const int64_t n1 = n0 + a.m;
+    // one more step to the chunk's end C-point n1
     level_step<CPT, NW, K, ST, RAG, ROE>(x, a.dt, a.psi_M, a, g, sm, a.pc, par);
-    if (a.g != nullptr) add_line(x, a.g + n1 * nx, g);
+    if (hg) {
+        if constexpr (!AHEAD) fetch_line<CPT, NW, RAG>(gn, a.g + n1 * nx, g);
+        add_line(x, gn);
+    }
     // the current value at that C-point
     const double* cnext = a.cref + (int64_t)(c + 1) * a.cref_stride * nx;
     if (a.resid_partial != nullptr) {
-        const double s = line_sqdiff(x, cnext, g, sm);
+        const double s = line_sqdiff<CPT, NW, RAG>(x, cnext, g, sm);
         if (threadIdx.x == 0) a.resid_partial[c] = s;
     }
     if (a.r_out != nullptr && g.active) {
+        double t[CPT];
+        fetch_line<CPT, NW, RAG>(t, cnext, g);
 #pragma unroll
         for (int q = 0; q < CPT; ++q)
-            if (q < g.nvalid) a.r_out[(int64_t)c * nx + g.j0 + q] = x[q] - cnext[g.j0 + q];
+            if (q < g.nvalid) a.r_out[(int64_t)c * nx + g.j0 + q] = x[q] - t[q];
     }
     if constexpr (END == END_CSTEP) {
         if (a.side_out != nullptr) store_line(x, a.side_out + (int64_t)(c + 1) * nx, g);
         return;
     }
     // END_RESTRICT: t = x; coarse guess and FAS right-hand side
-    if (a.coarse_injection) copy_line(cnext, a.uc_out + (int64_t)(c + 1) * nx, g);
+    if (a.coarse_injection) copy_line<CPT, NW, RAG>(cnext, a.uc_out + (int64_t)(c + 1) * nx, g);
     else store_line(x, a.uc_out + (int64_t)(c + 1) * nx, g);
     if (a.coarse_split) {
         store_line(x, a.gc_out + (int64_t)(c + 1) * nx, g);
         return;
     }
     double y[CPT];
-    load_line(y, cstart, g);
+    load_line<CPT, NW, RAG>(y, cstart, g);
     PhiConst pcn = a.pc;
     if (a.alpha_next > 0.0) pcn.alpha_fixed = a.alpha_next;
     level_step<CPT, NW, K, ST, RAG, ROE>(y, a.dt_next, a.psi_M_next, a, g, sm, pcn, par);

@@ -441,6 +441,7 @@ __device__ __forceinline__ void sys_body(const SweepArgs& a, const int c)
 #pragma unroll
     for (int d = 0; d < D; ++d) x[d] = 0.0;
     sys_load(x, src, g);
+    wait_loads();  // (as in sweep_body_t)
     if (a.ucommit != nullptr) sys_store(x, a.ucommit + (int64_t)c * a.ucommit_stride * nx, g);
     if (a.inject_last && c == a.nchunks - 1) {
         const double* last = (a.side_in != nullptr) ? a.side_in + (int64_t)a.nchunks * nx

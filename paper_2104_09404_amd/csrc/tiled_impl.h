@@ -451,13 +451,31 @@ __device__ __forceinline__ void t_store(const double (&x)[CPT], double* dst, con
         if (q < g.nvalid) dst[g.x0 + g.j0 + q] = x[q];
 }
 
-template <int CPT, int NW>
+// x += the tile's cells of line src (and the ghost): every load is issued
+// before any is used, in bounds and without a branch (a lane that owns no
+// cell reads the tile's first cells, the ragged lane its last cell in place
+// of the missing ones, a lane without a ghost cell 0), and the add covers
+// every slot: the stage code writes to LDS and reduces only owned cells and
+// the ghosts of lanes gk >= 0, and stores skip the rest.  (Loads under
+// per-cell predicates would be waited for one at a time.)
+template <int CPT, int NW, bool RAG>
 __device__ __forceinline__ void t_add(double (&x)[CPT], double& gx, const double* src, const TGeo<CPT, NW>& g)
 {
+    const double* base = src + g.x0;
+    const int j0 = g.active ? g.j0 : 0;
+    double t[CPT];
+    if constexpr (RAG) {
+        const int last = g.active ? g.nvalid - 1 : 0;
 #pragma unroll
-    for (int q = 0; q < CPT; ++q)
-        if (q < g.nvalid) x[q] = x[q] + src[g.x0 + g.j0 + q];
-    if (g.gk >= 0) gx = gx + src[g.gcell];
+        for (int q = 0; q < CPT; ++q) t[q] = base[j0 + (q < last ? q : last)];
+    } else {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) t[q] = base[j0 + q];
+    }
+    const double gt = src[g.gcell];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) x[q] = x[q] + t[q];
+    gx = gx + gt;
 }
 
 template <int CPT, int NW>
@@ -501,6 +519,7 @@ __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGe
                                                         : a.ustart + (int64_t)c * a.ustart_stride * nx;
     double x[CPT], gx;
     t_load(x, gx, src, g);
+    wait_loads();  // (as in sweep_body_t)
     if (a.ucommit != nullptr) t_store(x, a.ucommit + (int64_t)c * a.ucommit_stride * nx, g);
     if (a.inject_last && c == a.nchunks - 1) {
         const double* last = (a.side_in != nullptr) ? a.side_in + (int64_t)a.nchunks * nx
@@ -516,7 +535,7 @@ __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGe
     const int64_t n0 = (int64_t)c * a.m;
     for (int j = 1; j <= a.nsteps; ++j) {
         if (!phi_t<CPT, NW, K, ST, RAG, ROE>(x, gx, a.dt, g, sm, a.pc, ts)) return false;
-        if (a.g != nullptr) t_add(x, gx, a.g + (n0 + j) * nx, g);
+        if (a.g != nullptr) t_add<CPT, NW, RAG>(x, gx, a.g + (n0 + j) * nx, g);
         if (a.fout != nullptr) {
             if (a.fout_every <= 1) t_store(x, a.fout + (n0 + j) * nx, g);
             else if ((n0 + j) % a.fout_every == 0) t_store(x, a.fout + ((n0 + j) / a.fout_every) * nx, g);
@@ -531,7 +550,7 @@ __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGe
     }
     const int64_t n1 = n0 + a.m;
     if (!phi_t<CPT, NW, K, ST, RAG, ROE>(x, gx, a.dt, g, sm, a.pc, ts)) return false;
-    if (a.g != nullptr) t_add(x, gx, a.g + n1 * nx, g);
+    if (a.g != nullptr) t_add<CPT, NW, RAG>(x, gx, a.g + n1 * nx, g);
     const double* cnext = a.cref + (int64_t)(c + 1) * a.cref_stride * nx;
     if (a.resid_partial != nullptr) {
         const double s = t_sqdiff(x, cnext, g, sm);
