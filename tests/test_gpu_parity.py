@@ -316,6 +316,36 @@ def test_launch_configurations_agree_bitwise(gpu):
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("nx", [1001, 1024])
+def test_cycle_launch_configurations(orc, gpu, nx):
+    """FCF cycles under every launch shape that covers the line: the step
+    loops of the coarse levels add the FAS right-hand side, read one step
+    ahead with up to 4 cells per thread and after the stages with 8, and a
+    ragged line (1001 cells) clamps the reads of its last thread.  Every shape
+    gives the oracle's iterates, and all of them the same bits."""
+    pb = stable_problem(nx, 64, 4, 3, 91 + nx)
+    so = orc.scheme(pb.nx, flux=pb.flux, k=pb.k, stepper=pb.stepper, a=pb.a)
+    uo, ho, _, _ = orc.mgrit(so, orc.params(pb.nt, pb.dt, 4, 3, relax=1, max_iter=2, tol=-1.0), pb.u0)
+    sg = gpu.scheme_from_problem(pb)
+    outs = []
+    try:
+        for cpt, w in [(4, 4), (8, 4), (4, 8), (8, 8), (2, 8), (1, 16), (2, 16)]:
+            gpu.set_kernel_config(nx, nx, cpt, w, latency=False)
+            gpu.set_kernel_config(nx, nx, cpt, w, latency=True)
+            ug = T(np.zeros((pb.nt + 1, nx)))
+            rc, hg, ng = gpu.cycle(sg, gpu.params(pb.nt, pb.dt, 4, 3, relax=1, max_iter=2, tol=-1.0), T(pb.u0), ug)
+            assert ng == 2
+            outs.append((H(ug), np.array(hg), (cpt, w)))
+    finally:
+        gpu.clear_kernel_config()
+    assert np.all(rel_lines(outs[0][0], uo) < TOL)
+    check_hist(outs[0][1], ho, np.linalg.norm(pb.u0) * 4)
+    for u, h, cfg in outs[1:]:
+        assert np.array_equal(u, outs[0][0]), cfg
+        # per-chunk partial norms are summed in a shape-dependent order
+        check_hist(h, outs[0][1], np.linalg.norm(pb.u0) * 4)
+
+
 # ---------------------------------------------------------------------------
 # the benchmark workload at full size (W1: N_x = 1024, N_T = 4096, m = 8, 3 levels, FCF)
 # ---------------------------------------------------------------------------
