@@ -7,6 +7,11 @@ Euler, eq Euler with gamma = 5/3), independently of the oracle's formulas:
   (readings R18, R19), Roe's flux consistent and upwind in supersonic flow;
 * constant states and conservation under Phi;
 * the characteristic-wise reconstruction exact on polynomial data;
+* alpha_LF of a system taken over the reconstructed states u^-/+ of every
+  interface (eq eigs), with the closed-form eigenvalues of sec 2.1.3;
+* the characteristic decomposition on the central cell's eigenvectors
+  (sec 2.1.1), through a stencil that varies along one closed-form
+  eigenvector of that cell;
 * order of accuracy on an exactly advected entropy wave (Euler) and by
   self-convergence (shallow water);
 * the shape of Fig. MGRITweno for both systems (s = 1 converges fastest).
@@ -251,3 +256,99 @@ def test_entropy_fix_inactive_in_shocks(orc, sysname):
         checked += 1
         near_sonic += int(np.any(np.abs(lam) < (lL - lam)))
     assert checked > 100 and near_sonic > 10, (checked, near_sonic)
+
+
+def closed_form_speeds(sysname, u):
+    """|lambda_k| of sec 2.1.3 written from the primitive variables:
+    v -/+ sqrt(g h) for shallow water, v - c, v, v + c with c^2 = gamma p / rho
+    for Euler (u holds one state per column)."""
+    if sysname == "sw":
+        h, v = u[0], u[1] / u[0]
+        c = np.sqrt(G * h)
+        return np.abs(np.stack([v - c, v + c]))
+    rho, v = u[0], u[1] / u[0]
+    p = (GAMMA - 1.0) * (u[2] - 0.5 * rho * v * v)
+    c = np.sqrt(GAMMA * p / rho)
+    return np.abs(np.stack([v - c, v, v + c]))
+
+
+def wavy_line(sysname, nx, seed):
+    """A periodic line with a steep front and a smooth hump, physical
+    everywhere (h, rho, p > 0) and with velocities of both signs."""
+    g = np.random.default_rng(seed)
+    x = (np.arange(nx) + 0.5) / nx
+    front = np.tanh((x - 0.3) * 40.0) * 0.3
+    hump = 0.2 * np.sin(2 * np.pi * x + g.uniform(0, 2 * np.pi))
+    if sysname == "sw":
+        h = 1.0 + front + hump
+        v = 0.8 * np.cos(2 * np.pi * x + g.uniform(0, 2 * np.pi))
+        return np.concatenate([h, h * v])
+    rho = 1.0 + front + hump
+    v = 0.9 * np.cos(2 * np.pi * x + g.uniform(0, 2 * np.pi))
+    p = 1.0 + 0.5 * front - hump
+    return np.concatenate([rho, rho * v, p / (GAMMA - 1.0) + 0.5 * rho * v * v])
+
+
+@pytest.mark.parametrize("sysname", ["sw", "euler"])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_lf_speed_is_taken_over_reconstructed_states(orc, sysname, k):
+    """eq eigs (sec 2.1.2): alpha_LF of a system is the largest |lambda_k| of
+    the closed-form eigenvalues over both reconstructed states u^- and u^+ of
+    every interface, not over the cell averages.  The line is chosen so that
+    the two maxima differ, and u^+/- come from the reconstruction that the
+    polynomial and reference-state pins fix."""
+    nx = 32
+    s = schemes(orc, sysname, nx, k=k)
+    u = wavy_line(sysname, nx, 40 + k)
+    D = u.size // nx
+    um, up = orc.sys_recon(s, u)
+    expect = max(closed_form_speeds(sysname, um.reshape(D, nx)).max(),
+                 closed_form_speeds(sysname, up.reshape(D, nx)).max())
+    from_averages = closed_form_speeds(sysname, u.reshape(D, nx)).max()
+    assert abs(expect - from_averages) > 1e-6 * expect, (expect, from_averages)
+    _, alpha = orc.spatial_operator(s, u)
+    assert abs(alpha - expect) <= 1e-14 * expect, (alpha, expect)
+
+
+@pytest.mark.parametrize("sysname", ["sw", "euler"])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_characteristic_reconstruction_on_central_cell(orc, sysname, k):
+    """sec 2.1.1 decomposes a cell's stencil on the eigenvectors of that
+    cell's own state u_c.  With the stencil u_j = u_c + s_j r_q(u_c), where
+    r_q is the closed-form right eigenvector (sec 2.1.3) and s_0 = 0 at the
+    central cell, the characteristic variables are constants except the q-th,
+    which is l_q.u_c + s_j.  Hence u^-_{i+1/2} = u_c + W(s) r_q(u_c) and
+    u^+_{i-1/2} = u_c + W(reversed s) r_q(u_c), W being the scalar WENO
+    pinned by the golden tables.  The s_j jump at amplitude 1e-3, where the
+    smoothness indicators are of the size of eps and W is far from linear, so
+    a decomposition on another cell's eigenvectors misses by about 1e-7.  The
+    bound 1e-11 allows for eq B's quadratic forms acting on the values
+    themselves: an offset of order 1 costs about 1e-15 in beta, a relative
+    1e-9 at beta ~ eps, which W turns into about 1e-12 at this amplitude."""
+    nx, i = 16, 8
+    s = schemes(orc, sysname, nx, k=k)
+    if sysname == "sw":
+        h, v = 1.2, 0.4
+        c = math.sqrt(G * h)
+        uc = sw_state(h, v)
+        vecs = [np.array([1.0, v - c]), np.array([1.0, v + c])]
+    else:
+        rho, v, p = 1.1, 0.3, 0.9
+        c = math.sqrt(GAMMA * p / rho)
+        uc = euler_state(rho, v, p)
+        H = (uc[2] + p) / rho
+        vecs = [np.array([1.0, v - c, H - v * c]), np.array([1.0, v, 0.5 * v * v]),
+                np.array([1.0, v + c, H + v * c])]
+    shapes = {1: [-0.4, 0.0, 1.0], 2: [-0.3, 0.1, 0.0, 1.0, 1.2],
+              3: [0.3, -0.2, 0.1, 0.0, 1.0, 1.1, 0.9]}
+    sj = 1e-3 * np.array(shapes[k])
+    D = uc.size
+    for q, r in enumerate(vecs):
+        line = np.tile(uc[:, None], (1, nx))
+        for j in range(2 * k + 1):
+            line[:, i - k + j] = uc + sj[j] * r
+        um, up = orc.sys_recon(s, line.reshape(-1))
+        want_m = uc + orc.weno_left(k, sj) * r
+        want_p = uc + orc.weno_left(k, sj[::-1].copy()) * r
+        np.testing.assert_allclose(um.reshape(D, nx)[:, i], want_m, rtol=0, atol=1e-11)
+        np.testing.assert_allclose(up.reshape(D, nx)[:, i], want_p, rtol=0, atol=1e-11)
