@@ -20,20 +20,43 @@ import torch
 from . import mgrit as M
 
 
+def _mgrit_forward_params(p: M.Params, nt: int, dt: float) -> M.Params:
+    """A copy of the caller's parameters with C-point storage, after checking
+    that they describe the solve being differentiated: the checkpoint buffer
+    holds nt/m + 1 lines of step dt, and it starts empty, so it cannot be the
+    initial iterate."""
+    if p.nt != nt:
+        raise ValueError("mgrit_params.nt = %d differs from nt = %d" % (p.nt, nt))
+    if p.dt != dt:
+        raise ValueError("mgrit_params.dt = %r differs from dt = %r" % (p.dt, dt))
+    if p.m < 2 or nt % p.m:
+        raise ValueError("nt = %d is not a multiple of the coarsening factor m = %d" % (nt, p.m))
+    if p.init != 0:
+        raise ValueError("mgrit_params.init must be 0: the checkpoint buffer is not an initial iterate")
+    q = M.Params.from_buffer_copy(p)
+    q.storage = 1
+    return q
+
+
 class _Solve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u0, scheme, dt, nt, every, solver, mparams, parallel_segments):
         u0c = u0.detach().contiguous()
         nx = scheme.nx
+        if u0c.dtype != torch.float64 or u0c.numel() != nx:
+            raise ValueError("u0 must hold nx = %d float64 cells" % nx)
+        if nt < 1:
+            raise ValueError("nt must be positive")
         if solver == "serial":
+            if every < 1 or nt % every:
+                raise ValueError("nt = %d is not a multiple of the checkpoint spacing %d" % (nt, every))
             ckpt = torch.empty((nt // every + 1, nx), dtype=torch.float64, device=u0.device)
             M.checkpoints(scheme, dt, nt, every, u0c, ckpt)
         elif solver == "mgrit":
-            p = mparams
-            if p is None:
+            if mparams is None:
                 raise ValueError("solver='mgrit' needs mgrit parameters")
+            p = _mgrit_forward_params(mparams, nt, dt)
             every = p.m
-            p.storage = 1
             ckpt = torch.empty((nt // every + 1, nx), dtype=torch.float64, device=u0.device)
             rc, hist, iters = M.cycle(scheme, p, u0c, ckpt)
             if rc != M.MGRIT_OK:
