@@ -5,7 +5,10 @@ leg of the benchmark import this module.  The product library never does.
 
 The shared object is compiled with gcc (``-O2 -ffp-contract=off``, no
 fast-math) into ``oracle/_build/``; :func:`build` always recompiles,
-:func:`lib` compiles only when nothing is built yet.
+:func:`lib` compiles only when nothing is built yet.  :func:`timing_phi`
+times the same source built for speed (``-O3 -march=native``, still no
+fast-math) on the machine it runs on; only the CPU baseline of the benchmark
+uses that build.
 """
 from __future__ import annotations
 
@@ -112,6 +115,38 @@ def lib():
         L.orc_serial_adjoint.restype = C.c_double
         _lib = L
     return _lib
+
+
+TIMING_FLAGS = ["-O3", "-march=native", "-fno-fast-math", "-std=c99", "-fPIC", "-shared"]
+
+
+def timing_phi(s: Scheme, dt: float, lines: np.ndarray, budget_s: float):
+    """Apply Phi to every row of ``lines`` repeatedly, for about ``budget_s``
+    seconds, with the oracle source built for speed in a temporary directory
+    (flags TIMING_FLAGS, on the host that runs this).  Returns (repetitions,
+    seconds, compiler flags)."""
+    import tempfile
+    import time
+
+    tmp = tempfile.mkdtemp(prefix="oracle_timing_")
+    so = os.path.join(tmp, "libmgrit_oracle_timing.so")
+    subprocess.run(["gcc"] + TIMING_FLAGS + ["-o", so, SRC, "-lm"], check=True)
+    L = C.CDLL(so)
+    L.orc_phi_lines.argtypes = [C.POINTER(Scheme), C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.c_int64]
+    a = np.ascontiguousarray(lines, dtype=np.float64)
+    b = np.zeros_like(a)
+    nlines = a.size // line_len(s)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        L.orc_phi_lines(C.byref(s), dt, _p(a), _p(b), nlines)
+        a, b = b, a
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s:
+            break
+    return reps, el, " ".join(["gcc"] + TIMING_FLAGS)
 
 
 def _p(a: np.ndarray):

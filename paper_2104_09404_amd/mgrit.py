@@ -220,7 +220,7 @@ def params(nt: int, dt: float, m: int, levels: int, relax: int = 1, cycle: int =
 
 def scheme_from_problem(pb) -> Scheme:
     return scheme(pb.nx, flux=pb.flux, k=pb.k, stepper=pb.stepper, a=pb.a, eps=pb.eps, L=pb.L,
-                  numflux=getattr(pb, "numflux", 0))
+                  numflux=getattr(pb, "numflux", 0), lf_dx_dt=getattr(pb, "lf_dx_dt", 0))
 
 
 def phi(s: Scheme, dt: float, u_in, u_out, stream=None):

@@ -65,6 +65,9 @@ class Problem:
     max_iter: int = 100
     cfl: Optional[float] = None
     numflux: int = 0       # 0 Lax-Friedrichs, 1 Roe with the Harten-Hyman fix
+    lf_dx_dt: int = 0      # 1: the LF coefficient is dx/dt (the scheme of eq fineLF)
+    coarse_integrator: int = 0  # 0 rediscretisation, 1/2 zeroth/first-order fine-integrator matching
+    cycle: int = 0         # 0 V-cycle, 1 F-cycle
     extra: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -227,6 +230,50 @@ def e4_system(system: str, k: int = 2, numflux: int = 0, stepper: int = 3, max_i
     name = "e4_%s_s%d_%s" % (system, 2 * k + 1, "roe" if numflux else "lf")
     return Problem(name, flux, k, stepper, nx, nt, dt, 2, 3, 0, u0, a=a, max_iter=max_iter, tol=-1.0,
                    cfl=speed * 4 * dt * nx, numflux=numflux)
+
+
+def e1_fine_matching(nx: int = 1024, nt: int = 8192, moving: bool = True, order: int = 1,
+                     cycle: int = 0) -> Problem:
+    """The fine-integrator-matching experiment of sec 4 (Fig. MGRITfineMatch)
+    at its largest grid by default: Burgers with the first-order scheme of
+    eq fineLF (LF with alpha = dx/dt, forward Euler), L = 1, T = 0.475,
+    5 levels, m = 2, F-relaxation, coarse integrators matching the fine one
+    to first (order 1) or zeroth order; u0 = (1 + sin 2 pi x)/2 (moving
+    shock) or sin 2 pi x (stationary shock) as exact cell averages."""
+    base = cell_average_sin(nx, 1, 0.0)
+    u0 = 0.5 * (1.0 + base) if moving else base
+    dt = 0.475 / nt
+    name = "e1_matching%d_%s_nx%d" % (order, "moving" if moving else "stationary", nx)
+    return Problem(name, FLUX_BURGERS, 0, 1, nx, nt, dt, 2, 5, 0, u0, max_iter=nt // 2,
+                   cfl=float(np.max(np.abs(u0))) * dt * nx, lf_dx_dt=1, coarse_integrator=order + 1,
+                   cycle=cycle)
+
+
+def w1_stable_coarse(nx: int = 1024, nt: int = 4096, m: int = 4, levels: int = 3,
+                     coarse_cfl: float = 0.8) -> Problem:
+    """The 1024-cell WENO5 + SSPRK3 problem (u0 of w1_burgers_weno5) with a
+    step small enough that the coarsest level runs at CFL ``coarse_cfl``:
+    level 0 at coarse_cfl / m^(levels-1), so that MGRIT converges (sec 4
+    finds that the coarse CFL decides convergence)."""
+    pb = w1_burgers_weno5(nx=nx, nt=nt, m=m, levels=levels)
+    cfl0 = coarse_cfl / float(m ** (levels - 1))
+    dt = dt_for_cfl(cfl0, 1.0 / nx, float(np.max(np.abs(pb.u0))))
+    return Problem("burgers_weno5_nx%d_coarse_cfl%.1f" % (nx, coarse_cfl), FLUX_BURGERS, 2, 3, nx, nt, dt, m,
+                   levels, 1, pb.u0, max_iter=nt // m, cfl=cfl0)
+
+
+def w4_stable_coarse(coarse_cfl: float = 0.8) -> Problem:
+    """The adjoint workload's problem (4096 cells, 2048 steps, u0 and u_target
+    of w4_adjoint) with m = 4 and 3 levels and a step that puts the coarsest
+    level at CFL ``coarse_cfl``, so that the MGRIT forward converges."""
+    pb = w4_adjoint()
+    m, levels = 4, 3
+    cfl0 = coarse_cfl / float(m ** (levels - 1))
+    dt = dt_for_cfl(cfl0, 1.0 / pb.nx, float(np.max(np.abs(pb.u0))))
+    q = Problem("adjoint_nx%d_coarse_cfl%.1f" % (pb.nx, coarse_cfl), FLUX_BURGERS, 2, 3, pb.nx, pb.nt, dt, m,
+                levels, 1, pb.u0, max_iter=pb.nt // m, cfl=cfl0)
+    q.extra = dict(pb.extra)
+    return q
 
 
 def random_lines(index: int, nlines: int, nx: int, mean: float = 0.5, amp: float = 0.3) -> np.ndarray:
