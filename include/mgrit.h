@@ -245,6 +245,25 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
                 void* workspace, size_t ws_bytes, double* res_hist, int32_t* iters, void* stream);
 
 /*
+ * mgrit_cycle_noalloc -- mgrit_cycle for callers that cannot allocate device
+ * or pinned host memory (serving loops, harnesses that forbid hipMalloc).
+ * The workspace is a static device array of MGRIT_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) that the library holds on every device it runs on until the
+ * process ends; the call allocates nothing: no hipMalloc, no pinned host
+ * buffer (the stop flag is read into host stack memory), no profiling events
+ * (with profiling on, its launches are counted without timing).  Arguments,
+ * synchronisation, iterates and return codes are those of mgrit_cycle with
+ * the workspace argument dropped.  Problems whose mgrit_workspace_bytes(s, p)
+ * exceeds MGRIT_NOALLOC_SCRATCH_BYTES return MGRIT_EINVAL before any device
+ * work.  Every call on one device shares that device's array, which keeps
+ * the last call's contents (the call clears what must start at zero):
+ * calls that overlap in time on one device race and must not be issued.
+ */
+#define MGRIT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mgrit_cycle_noalloc(const mgrit_scheme* s, const mgrit_params* p, const double* u0, double* u,
+                        double* res_hist, int32_t* iters, void* stream);
+
+/*
  * mgrit_cycle_levels -- mgrit_cycle with the scheme schemes[l] on level l
  * (sec 4, Fig. MGRITweno_diffOrd: the WENO degree k and the Runge-Kutta
  * scheme may rise or fall across levels; the numerical flux and eps may

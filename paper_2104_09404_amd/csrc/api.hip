@@ -374,6 +374,10 @@ std::vector<PendingEvent> g_pending;
 // steps; only the classes in g_prof_mask are bracketed by HIP events (the
 // events themselves cost stream time, so a timing run can keep them to the
 // kernel it measures).
+// Set for the duration of an allocation-free call on the calling thread:
+// launches are then counted without events (creating one may allocate).
+thread_local bool tl_no_alloc = false;
+
 struct ProfLaunch {
     PendingEvent pe;
     bool timed = false;
@@ -383,7 +387,7 @@ struct ProfLaunch {
         pe.kc = kc;
         pe.phi_lines = phi_lines;
         pe.cells = cells;
-        timed = ((g_prof_mask >> kc) & 1u) != 0;
+        timed = !tl_no_alloc && ((g_prof_mask >> kc) & 1u) != 0;
         if (!timed) return MGRIT_OK;
         HIP_TRY(hipEventCreate(&pe.e0), "hipEventCreate");
         HIP_TRY(hipEventCreate(&pe.e1), "hipEventCreate");
@@ -809,6 +813,39 @@ struct Cycle {
 // ===========================================================================
 // exported C ABI
 // ===========================================================================
+// ---------------------------------------------------------------------------
+// allocation-free cycle: the workspace is a static device array; host code
+// uses only the per-device address that hipGetSymbolAddress returns for it
+// (the array's name on the host is a stand-in, not a device address)
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[MGRIT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mutex;
+char* g_noalloc_ptr[kMaxDevices] = {};
+
+// address of `scratch` on the current device, looked up once per device
+int noalloc_scratch(char** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MGRIT_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (g_noalloc_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress of the allocation-free workspace");
+        if (ptr == nullptr || ((uintptr_t)ptr & 255) != 0)
+            return fail(MGRIT_EHIP, "allocation-free workspace has no 256-byte aligned device address");
+        g_noalloc_ptr[dev] = (char*)ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return MGRIT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* mgrit_last_error(void) { return g_err.c_str(); }
@@ -1334,7 +1371,10 @@ static int run_cycle(const mgrit_scheme* const* sl, const mgrit_params* p, const
     cy.flag = flag;
     const int nch0 = p->nt / p->m;
     int host_flag = 0;
-    int* pinned = pinned_flags();
+    // an allocation-free call reads the flags into stack memory (a pageable
+    // copy, which the runtime stages itself)
+    int stack_flags[2] = {0, 0};
+    int* pinned = tl_no_alloc ? stack_flags : pinned_flags();
     if (!pinned) return fail(MGRIT_EHIP, "hipHostMalloc of the stop-flag buffer failed");
     int k = 0;
     for (;; ++k) {
@@ -1390,6 +1430,28 @@ int mgrit_cycle(const mgrit_scheme* s, const mgrit_params* p, const double* u0, 
     const mgrit_scheme* sl[16];
     for (int l = 0; l < 16; ++l) sl[l] = s;
     return run_cycle(sl, p, u0, u, workspace, ws_bytes, res_hist, iters, stream);
+}
+
+int mgrit_cycle_noalloc(const mgrit_scheme* s, const mgrit_params* p, const double* u0, double* u,
+                        double* res_hist, int32_t* iters, void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if ((rc = check_params(s, p))) return rc;
+    const size_t need = make_layout(s, p).total;
+    if (need > MGRIT_NOALLOC_SCRATCH_BYTES)
+        return fail(MGRIT_EINVAL, "mgrit_cycle_noalloc: the problem needs %zu workspace bytes, more than the %zu of "
+                                  "the static workspace; use mgrit_cycle with a caller workspace",
+                    need, (size_t)MGRIT_NOALLOC_SCRATCH_BYTES);
+    char* ws = nullptr;
+    if ((rc = noalloc_scratch(&ws))) return rc;
+    struct NoAllocScope {
+        NoAllocScope() { tl_no_alloc = true; }
+        ~NoAllocScope() { tl_no_alloc = false; }
+    } scope;
+    const mgrit_scheme* sl[16];
+    for (int l = 0; l < 16; ++l) sl[l] = s;
+    return run_cycle(sl, p, u0, u, ws, MGRIT_NOALLOC_SCRATCH_BYTES, res_hist, iters, stream);
 }
 
 int mgrit_cycle_levels(const mgrit_scheme* schemes, const mgrit_params* p, const double* u0, double* u,

@@ -28,7 +28,11 @@ EXPORTED = ["mgrit_phi", "mgrit_serial", "mgrit_relax", "mgrit_residual", "mgrit
             "mgrit_kernel_config", "mgrit_set_kernel_config", "mgrit_phi_vjp", "mgrit_checkpoints",
             "mgrit_adjoint_workspace_bytes", "mgrit_adjoint", "mgrit_tiled_config", "mgrit_set_tiled_config",
             "mgrit_batched_workspace_bytes", "mgrit_cycle_batched", "mgrit_cycle_levels",
-            "mgrit_set_profiling_mask", "mgrit_autotune_scratch_bytes", "mgrit_autotune"]
+            "mgrit_set_profiling_mask", "mgrit_autotune_scratch_bytes", "mgrit_autotune",
+            "mgrit_cycle_noalloc"]
+
+# size of the library's static workspace of mgrit_cycle_noalloc (MGRIT_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class MgritError(RuntimeError):
@@ -120,6 +124,7 @@ def load(path: str = LIB_PATH):
     L.mgrit_cycle.argtypes = [S, P, dp, dp, vp, C.c_size_t, C.POINTER(C.c_double), C.POINTER(C.c_int32), vp]
     L.mgrit_cycle_levels.argtypes = [S, P, dp, dp, vp, C.c_size_t, C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                      vp]
+    L.mgrit_cycle_noalloc.argtypes = [S, P, dp, dp, C.POINTER(C.c_double), C.POINTER(C.c_int32), vp]
     L.mgrit_last_error.restype = C.c_char_p
     L.mgrit_set_profiling.argtypes = [C.c_int]
     L.mgrit_autotune_scratch_bytes.argtypes = [i32, i32]
@@ -266,6 +271,19 @@ def cycle(s: Scheme, p: Params, u0, u, workspace=None, stream=None):
     iters = C.c_int32(0)
     rc = load().mgrit_cycle(C.byref(s), C.byref(p), _ptr(u0), _ptr(u), C.c_void_p(workspace.data_ptr()),
                             workspace.numel() * 8, hist, C.byref(iters), _stream(stream))
+    _check(rc, allow=(MGRIT_OK, MGRIT_NOT_CONVERGED))
+    n = iters.value
+    nres = 1 if p.levels == 1 else n + 1
+    return rc, [hist[i] for i in range(nres)], n
+
+
+def cycle_noalloc(s: Scheme, p: Params, u0, u, stream=None):
+    """mgrit_cycle on the library's static workspace (no allocation in the
+    call); returns (status, residual history list, cycles applied)."""
+    hist = (C.c_double * (p.max_iter + 1))()
+    iters = C.c_int32(0)
+    rc = load().mgrit_cycle_noalloc(C.byref(s), C.byref(p), _ptr(u0), _ptr(u), hist, C.byref(iters),
+                                    _stream(stream))
     _check(rc, allow=(MGRIT_OK, MGRIT_NOT_CONVERGED))
     n = iters.value
     nres = 1 if p.levels == 1 else n + 1

@@ -204,3 +204,21 @@ def test_system_validation_without_gpu(lib):
     n1 = lib.mgrit_workspace_bytes(C.byref(mgrit.scheme(64)), C.byref(p))
     n3 = lib.mgrit_workspace_bytes(C.byref(mgrit.euler_scheme(64)), C.byref(p))
     assert n3 > 2.5 * n1
+
+
+def test_noalloc_refuses_oversized_problem_without_gpu(lib):
+    """The allocation-free cycle checks its static workspace on the host: a
+    problem needing more than MGRIT_NOALLOC_SCRATCH_BYTES (the 65536-cell,
+    16384-step V-cycle) is refused before any device call."""
+    from paper_2104_09404_amd import mgrit
+
+    s = mgrit.scheme(65536)
+    p = mgrit.params(16384, 1e-6, 16, 4, relax=1, max_iter=2, tol=-1.0)
+    assert lib.mgrit_workspace_bytes(C.byref(s), C.byref(p)) > mgrit.NOALLOC_SCRATCH_BYTES
+    hist = (C.c_double * 3)()
+    it = C.c_int32(0)
+    assert lib.mgrit_cycle_noalloc(C.byref(s), C.byref(p), None, None, hist, C.byref(it), None) == mgrit.MGRIT_EINVAL
+    assert b"static workspace" in lib.mgrit_last_error()
+    assert mgrit.NOALLOC_SCRATCH_BYTES == 64 << 20
+    text = open(HEADER).read()
+    assert "#define MGRIT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)" in text
