@@ -472,8 +472,11 @@ def main():
     mgrit.load()
     pb = W.w2_burgers_weno5_large()
     cpt, nw, tiles = mgrit.tiled_config(pb.nx)
+    pair = mgrit.tiled_intervals(pb.nx) == 2
     rag = not (pb.nx % tiles == 0 and (pb.nx // tiles) % cpt == 0)
-    kernel = "tiled_relax_fc_kernel<%d, %d, 2, 3, %s, false>" % (cpt, nw, "true" if rag else "false")
+    # template arguments: cells per thread, waves, WENO degree, stages, ragged, Roe, two chunks per workgroup
+    kernel = "tiled_relax_fc_kernel<%d, %d, 2, 3, %s, false, %s>" % (cpt, nw, "true" if rag else "false",
+                                                                     "true" if pair else "false")
     r = run_cycles(mgrit, pb, args.steps, args.warmup)
     nch = pb.nt // pb.m
     out = {

@@ -11,12 +11,13 @@
  *   - All array pointers are DEVICE pointers to contiguous FP64 data owned by
  *     the caller (e.g. torch tensors).  The library never allocates or frees
  *     caller memory.  It allocates device memory only once per device: the
- *     3.1 MB synchronisation buffer of split lines (below), on the first
+ *     4.2 MB synchronisation buffer of split lines (below), on the first
  *     split-line launch outside mgrit_cycle, kept until the process ends.
  *   - Line length.  Lines of up to 4096 cells run on one workgroup each.
  *     Longer lines (or any range chosen with mgrit_set_tiled_config) are split
- *     into tiles of balanced length, one workgroup per tile, which meet once
- *     per Runge-Kutta stage through a global counter; their launches are
+ *     into tiles of balanced length, one workgroup per tile, which exchange
+ *     alpha_LF and their edge fluxes once per Runge-Kutta stage through
+ *     device memory; their launches are
  *     cooperative (all workgroups of a line resident at once).  Results are
  *     bitwise the same as with one workgroup per line.  Split-line calls
  *     outside mgrit_cycle that overlap in time on one device (different
@@ -381,6 +382,21 @@ int mgrit_tiled_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves, in
    cells_per_thread == 0 clears every such setting.  Lines must give tiles of
    at least 3 cells.  Not thread safe. */
 int mgrit_set_tiled_config(int32_t nx_lo, int32_t nx_hi, int32_t cells_per_thread, int32_t waves);
+
+/* the same with the number of time intervals (chunks) each workgroup of a
+   split line advances together: 1, or 2 (the two chunks run half a
+   Runge-Kutta stage apart, so that one chunk's exchange with the other tiles
+   overlaps the other chunk's reconstruction; results are bitwise those of
+   one chunk per workgroup).  Two intervals are compiled for (4, 8), whose
+   workgroup then keeps up to 256 VGPRs (2 waves per SIMD).  The setting is
+   cleared with the others by
+   mgrit_set_tiled_config(.., 0, ..).  Not thread safe. */
+int mgrit_set_tiled_intervals(int32_t nx_lo, int32_t nx_hi, int32_t cells_per_thread, int32_t waves,
+                              int32_t intervals);
+
+/* intervals per workgroup of the split-line configuration for lines of nx
+   cells (1 when such a line runs on one workgroup) */
+int mgrit_tiled_intervals(int32_t nx, int32_t* intervals);
 
 /* override the configuration for line lengths nx_lo..nx_hi in latency-bound
    (latency != 0) or throughput launches (mgrit_autotune installs its choice

@@ -148,8 +148,20 @@ struct TiledOverride {
 };
 std::vector<TiledOverride> g_tiled_overrides;
 
-bool tiled_compiled(int cpt, int nw)
+const KernelCfg kTiledPairCfgs[] = {
+#define MGK_ENTRY(C, W) {C, W, 2},
+    MGK_TILED_PAIR_CFG_LIST(MGK_ENTRY)
+#undef MGK_ENTRY
+};
+
+bool tiled_compiled(int cpt, int nw, int intervals = 1)
 {
+    if (intervals == 2) {
+        for (const KernelCfg& c : kTiledPairCfgs)
+            if (c.cpt == cpt && c.nw == nw) return true;
+        return false;
+    }
+    if (intervals != 1) return false;
     for (const KernelCfg& c : kTiledCfgs)
         if (c.cpt == cpt && c.nw == nw) return true;
     return false;
@@ -964,6 +976,25 @@ int mgrit_tiled_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves, in
     if (cells_per_thread) *cells_per_thread = c.cpt;
     if (waves) *waves = c.nw;
     if (tiles) *tiles = G;
+    return MGRIT_OK;
+}
+
+int mgrit_tiled_intervals(int32_t nx, int32_t* intervals)
+{
+    KernelCfg c{0, 0};
+    int G = 1;
+    if (intervals) *intervals = choose_tiled(nx, &c, &G) ? c.intervals : 1;
+    return MGRIT_OK;
+}
+
+int mgrit_set_tiled_intervals(int32_t nx_lo, int32_t nx_hi, int32_t cpt, int32_t waves, int32_t intervals)
+{
+    if (intervals != 1 && intervals != 2) return fail(MGRIT_EINVAL, "intervals per workgroup must be 1 or 2");
+    if (nx_lo > nx_hi || nx_lo < 8) return fail(MGRIT_EINVAL, "empty range or nx_lo < 8");
+    if (!tiled_compiled(cpt, waves, intervals))
+        return fail(MGRIT_EINVAL, "split-line configuration (%d, %d) with %d interval(s) per workgroup is not compiled",
+                    cpt, waves, intervals);
+    g_tiled_overrides.insert(g_tiled_overrides.begin(), TiledOverride{nx_lo, nx_hi, KernelCfg{cpt, waves, intervals}});
     return MGRIT_OK;
 }
 

@@ -233,6 +233,21 @@ hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_
     return hipGetLastError();
 }
 
+__global__ void fill_u64_kernel(unsigned long long* p, unsigned long long value, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long value, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t want = (n + 255) / 256;
+    const int blocks = want < 1024 ? (int)want : 1024;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks), dim3(256), 0, s, p, value, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_clear_ints(int* p, int n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;

@@ -110,13 +110,20 @@ struct BatchNorm {
 constexpr int kTileSlot = 16;
 constexpr int kTileCounterStride = 16;
 constexpr int kTileMaxWorkgroups = 8192;
+// forward split-line sweeps publish into a ring of 3 slots per tile (the
+// adjoint uses 2, by parity)
+constexpr int kTileRing = 3;
+// bit pattern of an empty slot value: a negative signalling NaN, which no
+// arithmetic result can be (results are quiet NaNs at most)
+constexpr unsigned long long kSlotEmpty = 0xFFF7DEADBEEF0001ull;
 inline size_t tile_sync_bytes()
 {
     return sizeof(unsigned long long) * kTileCounterStride * (size_t)(kTileMaxWorkgroups + 1);
 }
 inline size_t tile_scratch_bytes()
 {
-    return tile_sync_bytes() + sizeof(double) * (size_t)kTileMaxWorkgroups * 2 * kTileSlot;
+    // two chunks per workgroup at most
+    return tile_sync_bytes() + sizeof(double) * (size_t)kTileMaxWorkgroups * 2 * kTileRing * kTileSlot;
 }
 
 // Adjoint launches (adjoint_impl.h): one workgroup per line b.
@@ -142,8 +149,9 @@ struct AdjArgs {
 };
 
 struct KernelCfg {
-    int cpt;  // cells per thread
-    int nw;   // waves per workgroup (= per line)
+    int cpt;            // cells per thread
+    int nw;             // waves per workgroup (= per line)
+    int intervals = 1;  // split lines: chunks a workgroup advances together (1 or 2)
 };
 
 // compiled (cells per thread, waves) pairs.  Many-line launches use few
@@ -195,6 +203,11 @@ struct KernelCfg {
 
 // (cells per thread, waves) pairs compiled for tiled lines; a tile holds at
 // most 64 * waves * cells per thread cells
+// (cells per thread, waves) pairs compiled for split lines with two chunks
+// per workgroup (two chunks' state needs up to 256 VGPRs, hence 8 waves)
+#define MGK_TILED_PAIR_CFG_LIST(X) \
+    X(4, 8)
+
 #define MGK_TILED_CFG_LIST(X) \
     X(1, 4)                   \
     X(2, 4)                   \
@@ -213,7 +226,7 @@ struct KernelCfg {
 
 inline size_t tiled_smem_bytes(int cpt, int nw)
 {
-    return sizeof(double) * (64 * (size_t)nw * (size_t)cpt + 7 + 2 * 64 * (size_t)nw + (size_t)nw + 40);
+    return sizeof(double) * (64 * (size_t)nw * (size_t)cpt + 7 + 2 * 64 * (size_t)nw + (size_t)nw + 2 * 40);
 }
 
 inline size_t smem_bytes(int cpt, int nw)
@@ -233,6 +246,7 @@ hipError_t launch_fill_wave(double* u, int64_t nx, int64_t nlines, hipStream_t s
 // systems (flux 2: shallow water, 3: Euler): one workgroup of `threads` per line
 hipError_t launch_sys(const SweepArgs& a, int threads, int flux, int k, int stepper, hipStream_t s);
 hipError_t launch_clear_ints(int* p, int n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long value, int64_t n, hipStream_t s);
 hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_t s);
 hipError_t launch_reduce_norm(const double* partial, int n, double* hist, int* counter, int* flag, double tol,
                               hipStream_t s);

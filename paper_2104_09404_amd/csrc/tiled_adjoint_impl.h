@@ -427,6 +427,7 @@ __device__ __forceinline__ void tiled_sync_view(const AdjArgs& a, int G, int til
 {
     ts.err = a.tile_sync;
     ts.cnt = a.tile_sync + kTileCounterStride * (1 + grp);
+    ts.ring = 2;
     ts.pub = a.tile_pub + (int64_t)grp * G * 2 * kTileSlot;
     ts.G = G;
     ts.tile = tile;
@@ -478,6 +479,10 @@ __global__ __launch_bounds__(64 * NW) void tiled_stage_store_kernel(AdjArgs a)
     g.init(a.nx, tile, G);
     TSync ts;
     tiled_sync_view<CPT, NW>(a, G, tile, grp, ts);
+    // the forward stages exchange through the sweeps' slot ring (op_A_t)
+    ts.cnt = nullptr;
+    ts.ring = kTileRing;
+    ts.pub = a.tile_pub + (int64_t)grp * G * kTileRing * kTileSlot;
     const int64_t nx = a.nx;
     const PhiConst& pc = a.pc;
     for (int64_t b = grp; b < a.nlines; b += a.groups) {
@@ -525,7 +530,7 @@ __global__ __launch_bounds__(64 * NW) void tiled_stage_store_kernel(AdjArgs a)
 }
 
 template <class Fn>
-static hipError_t launch_coop_adj(Fn fn, const AdjArgs& a, int nw, size_t shmem, hipStream_t s)
+static hipError_t launch_coop_adj(Fn fn, const AdjArgs& a, int nw, size_t shmem, bool forward, hipStream_t s)
 {
     hipError_t e;
     if (shmem > 65536) {
@@ -544,6 +549,12 @@ static hipError_t launch_coop_adj(Fn fn, const AdjArgs& a, int nw, size_t shmem,
     b.groups = (int)std::min((long long)a.nlines, cap / G);
     e = launch_clear_ints((int*)b.tile_sync, 2 * kTileCounterStride * (b.groups + 1), s);
     if (e != hipSuccess) return e;
+    if (forward) {
+        // forward stages: every slot of the launch's groups starts empty
+        e = launch_fill_u64((unsigned long long*)b.tile_pub, kSlotEmpty, (int64_t)b.groups * G * kTileRing * kTileSlot,
+                            s);
+        if (e != hipSuccess) return e;
+    }
     void* args[] = {(void*)&b};
     return hipLaunchCooperativeKernel((const void*)fn, dim3((unsigned)(b.groups * G)), dim3(64 * nw), args,
                                       (unsigned)shmem, s);
@@ -561,8 +572,8 @@ hipError_t launch_tiled_adjoint_ks(const AdjArgs& a, const KernelCfg& cfg, int s
             (nx + G - 1) / G > 64 * W * C)                                                                    \
             return hipErrorInvalidValue;                                                                      \
         if (store_mode)                                                                                       \
-            return launch_coop_adj(tiled_stage_store_kernel<C, W, K, ST>, a, W, tiled_smem_bytes(C, W), s);   \
-        return launch_coop_adj(tiled_adjoint_kernel<C, W, K, ST>, a, W, tiled_adj_smem_bytes<C, W>(), s);     \
+            return launch_coop_adj(tiled_stage_store_kernel<C, W, K, ST>, a, W, tiled_smem_bytes(C, W), true, s); \
+        return launch_coop_adj(tiled_adjoint_kernel<C, W, K, ST>, a, W, tiled_adj_smem_bytes<C, W>(), false, s); \
     }
     MGK_TADJ_CFG_LIST(MGK_TADJ_CASE)
 #undef MGK_TADJ_CASE

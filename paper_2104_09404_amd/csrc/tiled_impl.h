@@ -14,10 +14,11 @@
 //          2F = Fa - alpha_LF Fb,  Fa = f(u^-) + f(u^+),  Fb = u^+ - u^-
 //      (with the Roe flux, eq roeflux, Fa is twice the flux and Fb = 0),
 //      and publishes its local max |u^{+-}| and (Fa, Fb) of the three
-//      interfaces inside each edge to a global slot;
-//   4. meets the other tiles of the line at a global counter (one arrival per
-//      tile, bounded spin), reads alpha_LF = max over all tiles (eq eigs) and
-//      its neighbours' edge data;
+//      interfaces inside each edge to a global slot, straight from the
+//      threads that hold them;
+//   4. polls the slots of the other tiles of the line (each value is its own
+//      arrival flag; bounded spin) for alpha_LF = max over all tiles (eq eigs)
+//      and its neighbours' edge data;
 //   5. updates its cells and, with the neighbours' data, its six ghost cells,
 //      evaluating exactly the operations the owners evaluate on the same
 //      operands, so ghosts stay bitwise equal to the owners' cells.
@@ -36,7 +37,7 @@ namespace mgk {
 
 constexpr long long kTileSpinLimit = 1LL << 22;
 
-// LDS: tl[T + 7] | bm[64 NW] | bp[64 NW] | amax[NW] | misc[40]
+// LDS: tl[T + 7] | bm[64 NW] | bp[64 NW] | amax[NW] | misc[40] | misc2[40]
 //   tl: the tile's cells transposed (cell c at (c mod CPT) * threads + c / CPT,
 //   so that every window position is read lane-contiguously, free of bank
 //   conflicts), ghost cells -3..-1 at T..T+2 and Tv..Tv+2 at T+3..T+5, one
@@ -44,7 +45,7 @@ constexpr long long kTileSpinLimit = 1LL << 22;
 //   misc[0] alpha_LF, [1..2] (Fa, Fb) of the tile's left edge interface,
 //   [3..4] of its right edge interface, [5..10] the left neighbour's
 //   right-edge data, [11..16] the right neighbour's left-edge data,
-//   [17..28] this tile's edge data staged for publication, [39] error flag
+//   [39] error flag; misc2 the same for the second chunk of a paired sweep
 template <int CPT, int NW>
 struct TSmem {
     double* tl;
@@ -52,6 +53,7 @@ struct TSmem {
     double* bp;
     double* amax;
     double* misc;
+    double* misc2;
     __device__ __forceinline__ void init(double* base)
     {
         tl = base;
@@ -59,6 +61,7 @@ struct TSmem {
         bp = bm + 64 * NW;
         amax = bp + 64 * NW;
         misc = amax + NW;
+        misc2 = misc + 40;
     }
 };
 
@@ -125,35 +128,71 @@ struct TGeo {
 
 // Per-workgroup view of the synchronisation scratch of its line group.
 struct TSync {
-    unsigned long long* cnt;  // arrival counter of the group (monotonic within a launch)
+    unsigned long long* cnt;  // arrival counter of the group (split-line adjoint only)
     unsigned long long* err;  // set when a spin times out; every workgroup then leaves
-    double* pub;              // slots of the group: (tile * 2 + parity) * kTileSlot
+    double* pub;              // slots of the group: (tile * kTileRing + stage % kTileRing) * kTileSlot
     int G;
     int tile;
-    long long ep;  // synchronisations done by this workgroup
-    __device__ __forceinline__ double* slot(int tl, int parity) const
+    long long ep;  // stages done by this workgroup
+    int ring;      // slots per tile: kTileRing (sweeps) or 2 (adjoint, by parity)
+    __device__ __forceinline__ double* slot(int tl, int r) const
     {
-        return pub + ((int64_t)tl * 2 + parity) * kTileSlot;
+        return pub + ((int64_t)tl * ring + r) * kTileSlot;
     }
 };
 
+// device-coherent accesses of the slots (no cache write-back or
+// invalidation of the whole L2 is involved)
 __device__ __forceinline__ double load_agent(const double* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned long long load_bits(const double* p)
+{
+    return __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_agent(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_empty(double* p)
+{
+    __hip_atomic_store((unsigned long long*)p, kSlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // A(V) on the tile (eq spaceDisc, eq LFflux) and on the ghost cell gv of
 // threads 0..5.  RAG: some tile of the line ends inside a thread.  Returns
 // false when the line's synchronisation failed.
 //
-// Published slot (one per tile and stage parity):
+// Published slot (one per tile and stage, in a ring of kTileRing):
 //   [0] max |u^{+-}| over the tile, [1..3] Fa at the right faces of tile cells
 //   0, 1, 2, [4..6] Fb there, [7..9] Fa at the left faces of cells Tv-3,
 //   Tv-2, Tv-1, [10..12] Fb there.
+// Every value is its own arrival flag: a slot holds kSlotEmpty until written,
+// and a reader polls each value it needs until it is no longer empty (64-bit
+// stores and loads are single-copy atomic).  Each value is written by the
+// thread that computed it (the max by thread 0 after the block reduction,
+// the edge fluxes by their owners), so no barrier gathers them first.
+// Reuse: the slot of stage s is emptied again by its writers right after
+// their tile has read every tile's stage s + 1 values, which proves that
+// every reader is done with stage s; its next use is stage s + 3.  A writer
+// waits for its emptying stores to complete before it publishes stage s + 2,
+// and a reader reads stage s + 3 only after it saw that writer's stage s + 2
+// value, so it can never take a value of stage s for one of stage s + 3.
+// The operator comes in two halves.  opA_begin mirrors V into LDS,
+// reconstructs, forms (Fa, Fb) of the thread's faces and publishes; opA_end
+// waits for every tile's values of the stage and forms A and gA.  misc is the
+// LDS area of the chunk (TSmem::misc, or misc2 for the second chunk of a
+// paired sweep).  Between the halves a workgroup may run the first half of
+// another chunk, whose reconstruction then hides the wait.
 template <int CPT, int NW, int K, bool RAG, bool ROE = false>
-__device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double (&A)[CPT], double& gA,
-                                       const TGeo<CPT, NW>& g, const TSmem<CPT, NW>& sm, const PhiConst& pc,
-                                       TSync& ts)
+__device__ __forceinline__ void opA_begin(const double (&V)[CPT], double gv, double (&Fa)[CPT + 1],
+                                          double (&Fb)[CPT + 1], const TGeo<CPT, NW>& g,
+                                          const TSmem<CPT, NW>& sm, double* misc, const PhiConst& pc,
+                                          const TSync& ts)
 {
     if (g.active) {
 #pragma unroll
@@ -253,7 +292,6 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
 
     const double uml = (g.t == 0) ? um_l : sm.bm[g.t - 1];
     const double upr = (g.t == g.tlast) ? up_r : sm.bp[min(g.t + 1, 64 * NW - 1)];
-    double Fa[CPT + 1], Fb[CPT + 1];
 #pragma unroll
     for (int q = 0; q <= CPT; ++q) {
         const double uL = (q == 0) ? uml : um[q - 1];
@@ -269,92 +307,128 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
         }
     }
 
-    // stage the edge data in LDS: right faces of cells 0..2, left faces of
-    // cells Tv-3..Tv-1, and the two edge interfaces themselves
-    if (g.active) {
+    // publish: the tile max (thread 0), the edge fluxes (their owners), each
+    // after the thread's earlier emptying stores have completed; stage the
+    // two edge interfaces of the tile itself in LDS for the ghost cells
+    const int r = (int)(ts.ep % kTileRing);
+    double* mine = ts.slot(ts.tile, r);
+    const bool edge_owner = g.active && (g.j0 < 3 || g.j0 + g.nvalid > g.Tv - 3);
+    if (threadIdx.x == 0 || edge_owner) __builtin_amdgcn_s_waitcnt(0);
+    if (threadIdx.x == 0) {
+        // the wave maxima stay in LDS until the next stage's reduction
+        double v = sm.amax[0];
+#pragma unroll
+        for (int w2 = 1; w2 < NW; ++w2) v = fmax(v, sm.amax[w2]);
+        store_agent(mine, v);
+    }
+    if (edge_owner) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
             const int cell = g.j0 + q;
             if (RAG && q >= g.nvalid) continue;
             if (cell < 3) {
-                sm.misc[17 + cell] = Fa[q + 1];
-                sm.misc[20 + cell] = Fb[q + 1];
+                store_agent(mine + 1 + cell, Fa[q + 1]);
+                store_agent(mine + 4 + cell, Fb[q + 1]);
             }
-            const int r = cell - (g.Tv - 3);
-            if (r >= 0) {
-                sm.misc[23 + r] = Fa[q];
-                sm.misc[26 + r] = Fb[q];
+            const int rr = cell - (g.Tv - 3);
+            if (rr >= 0) {
+                store_agent(mine + 7 + rr, Fa[q]);
+                store_agent(mine + 10 + rr, Fb[q]);
             }
         }
+    }
+    if (g.active) {
         if (g.t == 0) {
-            sm.misc[1] = Fa[0];
-            sm.misc[2] = Fb[0];
+            misc[1] = Fa[0];
+            misc[2] = Fb[0];
         }
         if (g.t == g.tlast) {
 #pragma unroll
             for (int q = 1; q <= CPT; ++q)
                 if (q == (RAG ? g.nvalid : CPT)) {
-                    sm.misc[3] = Fa[q];
-                    sm.misc[4] = Fb[q];
+                    misc[3] = Fa[q];
+                    misc[4] = Fb[q];
                 }
         }
     }
-    __syncthreads();
+}
 
-    // thread 0 publishes and arrives; wave 0 waits for the group
-    const int parity = ts.ep & 1;
+template <int CPT, int NW, bool RAG, bool ROE = false>
+__device__ __forceinline__ bool opA_end(const double (&Fa)[CPT + 1], const double (&Fb)[CPT + 1],
+                                        double (&A)[CPT], double& gA, const TGeo<CPT, NW>& g,
+                                        const TSmem<CPT, NW>& sm, double* misc, const PhiConst& pc, TSync& ts)
+{
+    // wave 0 polls the G tile maxima and the neighbours' 12 edge values
+    const int r = (int)(ts.ep % kTileRing);
     ts.ep += 1;
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
-        // lanes 0..12 publish the slot with device-coherent stores; waiting for
-        // their completion before the arrival orders them before it for any
-        // reader that sees the arrival (readers use device-coherent loads), so
-        // no cache write-back or invalidation of the whole L2 is needed
-        if (lane < 13) {
-            double v;
-            if (lane == 0) {
-                v = sm.amax[0];
-#pragma unroll
-                for (int w2 = 1; w2 < NW; ++w2) v = fmax(v, sm.amax[w2]);
+        const int G = ts.G;
+        double mx = 0.0;
+        int bad = 0;
+        for (int it = lane; it < G + 12; it += 64) {
+            const double* src;
+            int dst = -1;
+            if (it < G) {
+                src = ts.slot(it, r);
             } else {
-                v = sm.misc[16 + lane];
+                // items G..G+5: the left neighbour's right-edge (Fa, Fb);
+                // G+6..G+11: the right neighbour's left-edge (Fa, Fb)
+                const int e = it - G;
+                const int nb = (e < 6) ? (ts.tile + G - 1) % G : (ts.tile + 1) % G;
+                src = ts.slot(nb, r) + ((e < 6) ? 7 + e : 1 + (e - 6));
+                dst = 5 + e;
             }
-            __hip_atomic_store(ts.slot(ts.tile, parity) + lane, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        if (lane == 0) {
-            __hip_atomic_fetch_add(ts.cnt, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned long long target = (unsigned long long)ts.G * (unsigned long long)ts.ep;
+            unsigned long long bits = load_bits(src);
             long long spins = 0;
-            double bad = 0.0;
-            while (__hip_atomic_load(ts.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            while (bits == kSlotEmpty) {
                 if (__hip_atomic_load(ts.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
                     ++spins > kTileSpinLimit) {
                     __hip_atomic_store(ts.err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    bad = 1.0;
+                    bad = 1;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(1);
+                bits = load_bits(src);
             }
-            sm.misc[39] = bad;
+            const double v = __longlong_as_double((long long)bits);
+            if (dst < 0) mx = fmax(mx, v);
+            else misc[dst] = bad ? 0.0 : v;
         }
-        double mx = 0.0;
-        for (int i = lane; i < ts.G; i += 64) mx = fmax(mx, load_agent(ts.slot(i, parity)));
         mx = wave_max(mx);
-        if (lane < 12) {
-            // lanes 0..5: the left neighbour's right-edge (Fa, Fb); 6..11: the
-            // right neighbour's left-edge (Fa, Fb)
-            const int nb = (lane < 6) ? (ts.tile + ts.G - 1) % ts.G : (ts.tile + 1) % ts.G;
-            const int idx = (lane < 6) ? 7 + lane : 1 + (lane - 6);
-            sm.misc[5 + lane] = load_agent(ts.slot(nb, parity) + idx);
+        const bool any_bad = __ballot(bad) != 0;
+        if (lane == 0) {
+            misc[0] = ROE ? 0.0 : (pc.alpha_fixed > 0.0) ? pc.alpha_fixed : lf_alpha(mx, pc.fa, pc.fb);
+            misc[39] = any_bad ? 1.0 : 0.0;
         }
-        if (lane == 0)
-            sm.misc[0] = ROE ? 0.0 : (pc.alpha_fixed > 0.0) ? pc.alpha_fixed : lf_alpha(mx, pc.fa, pc.fb);
     }
     __syncthreads();
 
-    const double alpha = sm.misc[0];
-    const bool ok = sm.misc[39] == 0.0;
+    // every tile has now published this stage, so every reader is done with
+    // the previous one: its writers empty that slot (used again 3 stages on)
+    {
+        double* old = ts.slot(ts.tile, (r + kTileRing - 1) % kTileRing);
+        if (threadIdx.x == 0) store_empty(old);
+        if (g.active) {
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                const int cell = g.j0 + q;
+                if (RAG && q >= g.nvalid) continue;
+                if (cell < 3) {
+                    store_empty(old + 1 + cell);
+                    store_empty(old + 4 + cell);
+                }
+                const int rr = cell - (g.Tv - 3);
+                if (rr >= 0) {
+                    store_empty(old + 7 + rr);
+                    store_empty(old + 10 + rr);
+                }
+            }
+        }
+    }
+
+    const double alpha = misc[0];
+    const bool ok = misc[39] == 0.0;
     double F2[CPT + 1];
 #pragma unroll
     for (int q = 0; q <= CPT; ++q) F2[q] = fma(-alpha, Fb[q], Fa[q]);
@@ -367,29 +441,39 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
         double faL, fbL, faR, fbR;
         const int k = g.gk;
         if (k < 2) {  // cells -3, -2: the left neighbour's faces
-            faL = sm.misc[5 + k];
-            fbL = sm.misc[8 + k];
-            faR = sm.misc[6 + k];
-            fbR = sm.misc[9 + k];
+            faL = misc[5 + k];
+            fbL = misc[8 + k];
+            faR = misc[6 + k];
+            fbR = misc[9 + k];
         } else if (k == 2) {  // cell -1: its right face is the tile's left edge
-            faL = sm.misc[7];
-            fbL = sm.misc[10];
-            faR = sm.misc[1];
-            fbR = sm.misc[2];
+            faL = misc[7];
+            fbL = misc[10];
+            faR = misc[1];
+            fbR = misc[2];
         } else if (k == 3) {  // cell Tv: its left face is the tile's right edge
-            faL = sm.misc[3];
-            fbL = sm.misc[4];
-            faR = sm.misc[11];
-            fbR = sm.misc[14];
+            faL = misc[3];
+            fbL = misc[4];
+            faR = misc[11];
+            fbR = misc[14];
         } else {  // cells Tv+1, Tv+2: the right neighbour's faces
-            faL = sm.misc[11 + (k - 4)];
-            fbL = sm.misc[14 + (k - 4)];
-            faR = sm.misc[12 + (k - 4)];
-            fbR = sm.misc[15 + (k - 4)];
+            faL = misc[11 + (k - 4)];
+            fbL = misc[14 + (k - 4)];
+            faR = misc[12 + (k - 4)];
+            fbR = misc[15 + (k - 4)];
         }
         gA = (fma(-alpha, fbL, faL) - fma(-alpha, fbR, faR)) * pc.half_inv_dx;
     }
     return ok;
+}
+
+template <int CPT, int NW, int K, bool RAG, bool ROE = false>
+__device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double (&A)[CPT], double& gA,
+                                       const TGeo<CPT, NW>& g, const TSmem<CPT, NW>& sm, const PhiConst& pc,
+                                       TSync& ts)
+{
+    double Fa[CPT + 1], Fb[CPT + 1];
+    opA_begin<CPT, NW, K, RAG, ROE>(V, gv, Fa, Fb, g, sm, sm.misc, pc, ts);
+    return opA_end<CPT, NW, RAG, ROE>(Fa, Fb, A, gA, g, sm, sm.misc, pc, ts);
 }
 
 // x <- Phi(x), ghost gx alongside (eq SSPRK1/2/3)
@@ -576,10 +660,191 @@ __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGe
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// paired sweeps: two chunks per workgroup
+// ---------------------------------------------------------------------------
+// A chunk is a fixed program of Phi applications ("jobs"): nsteps F-steps,
+// then the role's end (one more Phi for the C-step, the FAS restriction or
+// END_PHI, and for the restriction a last Phi of the chunk-start line with the
+// coarse step).  Each job is ST stages.  A paired sweep runs two chunks A and B
+// of the same group in lock step, offset by half a stage:
+//     begin(A, s)  begin(B, s)  end(A, s)  begin(A, s+1)  end(B, s)  begin(B, s+1)  end(A, s+1) ...
+// so that every wait for the other tiles (end) follows the reconstruction of
+// the other chunk, which covers the latency of the device-memory exchange.
+// Each chunk has its own slots (and ring) and its own LDS area; the per-cell
+// operations are those of tiled_chunk, so the results are bitwise the same.
+template <int CPT>
+struct TLane {
+    double x[CPT], gx;                 // Phi input, then its result
+    double v[CPT], gv;                 // intermediate Runge-Kutta stage
+    double Fa[CPT + 1], Fb[CPT + 1];   // published fluxes, waiting for alpha_LF
+    double xs[CPT];                    // restriction: the C-point result while the start line is stepped
+    int c;                             // chunk
+};
+
+template <int END>
+__device__ __forceinline__ int chunk_jobs(const SweepArgs& a)
+{
+    return a.nsteps + (END == END_NONE ? 0 : (END == END_RESTRICT ? 2 : 1));
+}
+
+// chunk c before its first stage (the preamble of tiled_chunk)
+template <int CPT, int NW, int END>
+__device__ __forceinline__ void lane_start(const SweepArgs& a, TLane<CPT>& L, const TGeo<CPT, NW>& g)
+{
+    const int64_t nx = a.nx;
+    const int c = L.c;
+    const double* src = (a.side_in != nullptr && c > 0) ? a.side_in + (int64_t)c * nx
+                                                        : a.ustart + (int64_t)c * a.ustart_stride * nx;
+    t_load(L.x, L.gx, src, g);
+    wait_loads();
+    if (a.ucommit != nullptr) t_store(L.x, a.ucommit + (int64_t)c * a.ucommit_stride * nx, g);
+    if (a.inject_last && c == a.nchunks - 1) {
+        const double* last = (a.side_in != nullptr) ? a.side_in + (int64_t)a.nchunks * nx
+                                                    : a.ustart + (int64_t)a.nchunks * a.ustart_stride * nx;
+        t_copy(last, a.ucommit + (int64_t)a.nchunks * a.ucommit_stride * nx, g);
+    }
+    if (END == END_RESTRICT && c == 0) {
+        const double* cstart = (a.ystart != nullptr) ? a.ystart : src;
+        t_copy(cstart, a.uc_out, g);
+        t_copy(a.g != nullptr ? a.g : cstart, a.gc_out, g);
+    }
+}
+
+// after the last stage of job j (tiled_chunk's work between Phi applications)
+template <int CPT, int NW, bool RAG, int END>
+__device__ __forceinline__ void lane_job_done(const SweepArgs& a, int j, TLane<CPT>& L, const TGeo<CPT, NW>& g,
+                                              const TSmem<CPT, NW>& sm, const TSync& ts)
+{
+    const int64_t nx = a.nx;
+    const int c = L.c;
+    const int64_t n0 = (int64_t)c * a.m;
+    if (j < a.nsteps) {
+        if (a.g != nullptr) t_add<CPT, NW, RAG>(L.x, L.gx, a.g + (n0 + j + 1) * nx, g);
+        if (a.fout != nullptr) {
+            if (a.fout_every <= 1) t_store(L.x, a.fout + (n0 + j + 1) * nx, g);
+            else if ((n0 + j + 1) % a.fout_every == 0) t_store(L.x, a.fout + ((n0 + j + 1) / a.fout_every) * nx, g);
+        }
+        return;
+    }
+    if constexpr (END == END_PHI) {
+        t_store(L.x, a.side_out + (int64_t)c * nx, g);
+        return;
+    }
+    if (j == a.nsteps) {
+        const int64_t n1 = n0 + a.m;
+        if (a.g != nullptr) t_add<CPT, NW, RAG>(L.x, L.gx, a.g + n1 * nx, g);
+        const double* cnext = a.cref + (int64_t)(c + 1) * a.cref_stride * nx;
+        if (a.resid_partial != nullptr) {
+            const double sq = t_sqdiff(L.x, cnext, g, sm);
+            if (threadIdx.x == 0) a.resid_partial[(int64_t)c * ts.G + ts.tile] = sq;
+        }
+        if (a.r_out != nullptr) {
+#pragma unroll
+            for (int q = 0; q < CPT; ++q)
+                if (q < g.nvalid) a.r_out[(int64_t)c * nx + g.x0 + g.j0 + q] = L.x[q] - cnext[g.x0 + g.j0 + q];
+        }
+        if constexpr (END == END_CSTEP) {
+            if (a.side_out != nullptr) t_store(L.x, a.side_out + (int64_t)(c + 1) * nx, g);
+            return;
+        }
+        if (a.coarse_injection) t_copy(cnext, a.uc_out + (int64_t)(c + 1) * nx, g);
+        else t_store(L.x, a.uc_out + (int64_t)(c + 1) * nx, g);
+        // the last job steps the chunk-start line with the coarse step
+        const double* src = (a.side_in != nullptr && c > 0) ? a.side_in + (int64_t)c * nx
+                                                            : a.ustart + (int64_t)c * a.ustart_stride * nx;
+        const double* cstart = (a.ystart != nullptr) ? a.ystart + (int64_t)c * a.ystart_stride * nx : src;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) L.xs[q] = L.x[q];
+        t_load(L.x, L.gx, cstart, g);
+        return;
+    }
+    // restriction: g_c = t - Phi_{l+1}(start line)
+    double y[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) y[q] = L.xs[q] - L.x[q];
+    t_store(y, a.gc_out + (int64_t)(c + 1) * nx, g);
+}
+
+// end of stage k of lane L, its Runge-Kutta combination, the job's end when
+// the stage was its last, and the first half of stage k + 1
+template <int CPT, int NW, int K, int ST, bool RAG, int END, bool ROE>
+__device__ __forceinline__ bool lane_step(const SweepArgs& a, int k, int nst, TLane<CPT>& L, const TGeo<CPT, NW>& g,
+                                          const TSmem<CPT, NW>& sm, double* misc, TSync& ts)
+{
+    double A[CPT], gA;
+    if (!opA_end<CPT, NW, RAG, ROE>(L.Fa, L.Fb, A, gA, g, sm, misc, a.pc, ts)) return false;
+    const int j = k / ST, st = k - j * ST;
+    const double dt = (END == END_RESTRICT && j == chunk_jobs<END>(a) - 1) ? a.dt_next : a.dt;
+    if (ST == 1) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) L.x[q] = rk_first(L.x[q], A[q], dt);
+        L.gx = rk_first(L.gx, gA, dt);
+    } else if (ST == 2) {
+        if (st == 0) {
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) L.v[q] = rk_first(L.x[q], A[q], dt);
+            L.gv = rk_first(L.gx, gA, dt);
+        } else {
+            const double hdt = 0.5 * dt;
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) L.x[q] = rk2_second(L.x[q], L.v[q], A[q], hdt);
+            L.gx = rk2_second(L.gx, L.gv, gA, hdt);
+        }
+    } else {
+        if (st == 0) {
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) L.v[q] = rk_first(L.x[q], A[q], dt);
+            L.gv = rk_first(L.gx, gA, dt);
+        } else if (st == 1) {
+            const double qdt = 0.25 * dt;
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) L.v[q] = rk3_second(L.x[q], L.v[q], A[q], qdt);
+            L.gv = rk3_second(L.gx, L.gv, gA, qdt);
+        } else {
+            const double tdt = (2.0 / 3.0) * dt;
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) L.x[q] = rk3_third(L.x[q], L.v[q], A[q], tdt);
+            L.gx = rk3_third(L.gx, L.gv, gA, tdt);
+        }
+    }
+    if (st == ST - 1) lane_job_done<CPT, NW, RAG, END>(a, j, L, g, sm, ts);
+    if (k + 1 < nst) {
+        const bool first = (st == ST - 1);
+        double V[CPT];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) V[q] = first ? L.x[q] : L.v[q];
+        opA_begin<CPT, NW, K, RAG, ROE>(V, first ? L.gx : L.gv, L.Fa, L.Fb, g, sm, misc, a.pc, ts);
+    }
+    return true;
+}
+
+// chunks cA and cB (cB < 0: none) on one tile
+template <int CPT, int NW, int K, int ST, bool RAG, int END, bool ROE>
+__device__ __forceinline__ bool tiled_pair(const SweepArgs& a, int cA, int cB, const TGeo<CPT, NW>& g,
+                                           const TSmem<CPT, NW>& sm, TSync& tsA, TSync& tsB)
+{
+    const bool two = cB >= 0;
+    TLane<CPT> LA, LB;
+    LA.c = cA;
+    LB.c = two ? cB : cA;
+    lane_start<CPT, NW, END>(a, LA, g);
+    if (two) lane_start<CPT, NW, END>(a, LB, g);
+    const int nst = chunk_jobs<END>(a) * ST;
+    if (nst == 0) return true;
+    opA_begin<CPT, NW, K, RAG, ROE>(LA.x, LA.gx, LA.Fa, LA.Fb, g, sm, sm.misc, a.pc, tsA);
+    if (two) opA_begin<CPT, NW, K, RAG, ROE>(LB.x, LB.gx, LB.Fa, LB.Fb, g, sm, sm.misc2, a.pc, tsB);
+    for (int k = 0; k < nst; ++k) {
+        if (!lane_step<CPT, NW, K, ST, RAG, END, ROE>(a, k, nst, LA, g, sm, sm.misc, tsA)) return false;
+        if (two && !lane_step<CPT, NW, K, ST, RAG, END, ROE>(a, k, nst, LB, g, sm, sm.misc2, tsB)) return false;
+    }
+    return true;
+}
+
 // Workgroup b: tile b % G of line group b / G; the group takes chunks
 // grp, grp + groups, ...  Every workgroup of a group runs the same sequence of
 // steps, hence the same sequence of synchronisations.
-template <int CPT, int NW, int K, int ST, bool RAG, int END, bool ROE>
+template <int CPT, int NW, int K, int ST, bool RAG, int END, bool ROE, bool PAIR>
 __device__ __forceinline__ void tiled_body_t(const SweepArgs& a)
 {
     if (a.flag != nullptr && *a.flag != 0) return;
@@ -592,47 +857,70 @@ __device__ __forceinline__ void tiled_body_t(const SweepArgs& a)
     TGeo<CPT, NW> g;
     g.init(a.nx, tile, G);
     TSync ts;
+    ts.cnt = nullptr;
+    ts.ring = kTileRing;
     ts.err = a.tile_sync;
-    ts.cnt = a.tile_sync + kTileCounterStride * (1 + grp);
-    ts.pub = a.tile_pub + (int64_t)grp * G * 2 * kTileSlot;
+    ts.pub = a.tile_pub + (int64_t)grp * (PAIR ? 2 : 1) * G * kTileRing * kTileSlot;
     ts.G = G;
     ts.tile = tile;
     ts.ep = 0;
-    for (int c = grp; c < a.nchunks; c += a.groups)
-        if (!tiled_chunk<CPT, NW, K, ST, RAG, END, ROE>(a, c, g, sm, ts)) return;
+    if constexpr (PAIR) {
+        // chunks grp, grp + groups, ... taken two at a time, each with its own slots
+        TSync ts2 = ts;
+        ts2.pub = ts.pub + (int64_t)G * kTileRing * kTileSlot;
+        for (int c = grp; c < a.nchunks; c += 2 * a.groups) {
+            const int c2 = c + a.groups;
+            if (!tiled_pair<CPT, NW, K, ST, RAG, END, ROE>(a, c, c2 < a.nchunks ? c2 : -1, g, sm, ts, ts2)) return;
+        }
+    } else {
+        for (int c = grp; c < a.nchunks; c += a.groups)
+            if (!tiled_chunk<CPT, NW, K, ST, RAG, END, ROE>(a, c, g, sm, ts)) return;
+    }
 }
 
 // The four roles as separately named kernels; ROE (the numerical flux) is a
 // kernel parameter, so that each flux gets its own register allocation.
-template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
-__global__ __launch_bounds__(64 * NW) void tiled_relax_f_kernel(SweepArgs a)
+// PAIR: two chunks per workgroup (tiled_pair); with fewer than 16 waves such
+// a workgroup keeps up to 256 VGPRs for the two chunks' state.
+// Whole-thread tiles are compiled for 4 waves per SIMD (at most 128 VGPRs):
+// with 16 waves that is one workgroup per compute unit either way, but the
+// schedule built for that occupancy ran the 65536-cell F-sweep 12 % faster
+// (15.0 against 16.9 ms); ragged tiles keep the compiler's budget, which
+// holds them free of register spills.
+#define MGK_TILED_WAVES_PER_EU (RAG ? 1 : (PAIR && NW < 16) ? 2 : 4)
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE, bool PAIR>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MGK_TILED_WAVES_PER_EU))) void tiled_relax_f_kernel(
+    SweepArgs a)
 {
-    tiled_body_t<CPT, NW, K, ST, RAG, END_NONE, ROE>(a);
+    tiled_body_t<CPT, NW, K, ST, RAG, END_NONE, ROE, PAIR>(a);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
-__global__ __launch_bounds__(64 * NW) void tiled_relax_fc_kernel(SweepArgs a)
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE, bool PAIR>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MGK_TILED_WAVES_PER_EU))) void tiled_relax_fc_kernel(
+    SweepArgs a)
 {
-    tiled_body_t<CPT, NW, K, ST, RAG, END_CSTEP, ROE>(a);
+    tiled_body_t<CPT, NW, K, ST, RAG, END_CSTEP, ROE, PAIR>(a);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
-__global__ __launch_bounds__(64 * NW) void tiled_relax_fr_kernel(SweepArgs a)
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE, bool PAIR>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MGK_TILED_WAVES_PER_EU))) void tiled_relax_fr_kernel(
+    SweepArgs a)
 {
-    tiled_body_t<CPT, NW, K, ST, RAG, END_RESTRICT, ROE>(a);
+    tiled_body_t<CPT, NW, K, ST, RAG, END_RESTRICT, ROE, PAIR>(a);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
-__global__ __launch_bounds__(64 * NW) void tiled_phi_kernel(SweepArgs a)
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE, bool PAIR>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MGK_TILED_WAVES_PER_EU))) void tiled_phi_kernel(
+    SweepArgs a)
 {
-    tiled_body_t<CPT, NW, K, ST, RAG, END_PHI, ROE>(a);
+    tiled_body_t<CPT, NW, K, ST, RAG, END_PHI, ROE, PAIR>(a);
 }
 
 // ---------------------------------------------------------------------------
 // cooperative, persistent launch
 // ---------------------------------------------------------------------------
 template <class Fn>
-static hipError_t launch_coop(Fn fn, const SweepArgs& a, int nw, size_t shmem, hipStream_t s)
+static hipError_t launch_coop(Fn fn, const SweepArgs& a, int nw, size_t shmem, bool pair, hipStream_t s)
 {
     hipError_t e;
     if (shmem > 65536) {
@@ -649,50 +937,59 @@ static hipError_t launch_coop(Fn fn, const SweepArgs& a, int nw, size_t shmem, h
     if (G < 1 || cap < G) return hipErrorCooperativeLaunchTooLarge;
     SweepArgs b = a;
     b.groups = (int)std::min((long long)a.nchunks, cap / G);
-    e = launch_clear_ints((int*)b.tile_sync, 2 * kTileCounterStride * (b.groups + 1), s);
+    // clear the error word and empty every slot of the launch's groups
+    e = launch_clear_ints((int*)b.tile_sync, 2, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u64((unsigned long long*)b.tile_pub, kSlotEmpty,
+                        (int64_t)b.groups * (pair ? 2 : 1) * G * kTileRing * kTileSlot, s);
     if (e != hipSuccess) return e;
     void* args[] = {(void*)&b};
     return hipLaunchCooperativeKernel((const void*)fn, dim3((unsigned)(b.groups * G)), dim3(64 * nw), args,
                                       (unsigned)shmem, s);
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE, bool PAIR>
 static hipError_t launch_tiled_role_f(const SweepArgs& a, hipStream_t s)
 {
     const size_t shmem = tiled_smem_bytes(CPT, NW);
     switch (a.end_mode) {
-    case END_NONE: return launch_coop(tiled_relax_f_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
-    case END_CSTEP: return launch_coop(tiled_relax_fc_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
-    case END_RESTRICT: return launch_coop(tiled_relax_fr_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
-    case END_PHI: return launch_coop(tiled_phi_kernel<CPT, NW, K, ST, RAG, ROE>, a, NW, shmem, s);
+    case END_NONE: return launch_coop(tiled_relax_f_kernel<CPT, NW, K, ST, RAG, ROE, PAIR>, a, NW, shmem, PAIR, s);
+    case END_CSTEP: return launch_coop(tiled_relax_fc_kernel<CPT, NW, K, ST, RAG, ROE, PAIR>, a, NW, shmem, PAIR, s);
+    case END_RESTRICT:
+        return launch_coop(tiled_relax_fr_kernel<CPT, NW, K, ST, RAG, ROE, PAIR>, a, NW, shmem, PAIR, s);
+    case END_PHI: return launch_coop(tiled_phi_kernel<CPT, NW, K, ST, RAG, ROE, PAIR>, a, NW, shmem, PAIR, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int CPT, int NW, int K, int ST, bool RAG>
+template <int CPT, int NW, int K, int ST, bool RAG, bool PAIR>
 static hipError_t launch_tiled_role(const SweepArgs& a, hipStream_t s)
 {
-    if (a.pc.roe) return launch_tiled_role_f<CPT, NW, K, ST, RAG, true>(a, s);
-    return launch_tiled_role_f<CPT, NW, K, ST, RAG, false>(a, s);
+    if (a.pc.roe) return launch_tiled_role_f<CPT, NW, K, ST, RAG, true, PAIR>(a, s);
+    return launch_tiled_role_f<CPT, NW, K, ST, RAG, false, PAIR>(a, s);
 }
 
 // The tile lengths (balanced, see TGeo) must lie in [3, 64 NW CPT]; the
 // launch is ragged unless every tile is a whole number of threads.
-template <int CPT, int NW, int K, int ST>
+template <int CPT, int NW, int K, int ST, bool PAIR>
 static hipError_t launch_tiled_cfg(const SweepArgs& a, hipStream_t s)
 {
     const int64_t nx = a.nx, G = a.tiles;
     if (G < 1 || nx / G < 3 || (nx + G - 1) / G > 64 * NW * CPT) return hipErrorInvalidValue;
-    if (nx % G == 0 && (nx / G) % CPT == 0) return launch_tiled_role<CPT, NW, K, ST, false>(a, s);
-    return launch_tiled_role<CPT, NW, K, ST, true>(a, s);
+    if (nx % G == 0 && (nx / G) % CPT == 0) return launch_tiled_role<CPT, NW, K, ST, false, PAIR>(a, s);
+    return launch_tiled_role<CPT, NW, K, ST, true, PAIR>(a, s);
 }
 
 template <int K, int ST>
 hipError_t launch_tiled_ks(const SweepArgs& a, const KernelCfg& cfg, hipStream_t s)
 {
 #define MGK_CASE(C, W) \
-    if (cfg.cpt == C && cfg.nw == W) return launch_tiled_cfg<C, W, K, ST>(a, s);
+    if (cfg.cpt == C && cfg.nw == W && cfg.intervals == 1) return launch_tiled_cfg<C, W, K, ST, false>(a, s);
     MGK_TILED_CFG_LIST(MGK_CASE)
+#undef MGK_CASE
+#define MGK_CASE(C, W) \
+    if (cfg.cpt == C && cfg.nw == W && cfg.intervals == 2) return launch_tiled_cfg<C, W, K, ST, true>(a, s);
+    MGK_TILED_PAIR_CFG_LIST(MGK_CASE)
 #undef MGK_CASE
     return hipErrorInvalidValue;
 }

@@ -29,7 +29,7 @@ EXPORTED = ["mgrit_phi", "mgrit_serial", "mgrit_relax", "mgrit_residual", "mgrit
             "mgrit_adjoint_workspace_bytes", "mgrit_adjoint", "mgrit_tiled_config", "mgrit_set_tiled_config",
             "mgrit_batched_workspace_bytes", "mgrit_cycle_batched", "mgrit_cycle_levels",
             "mgrit_set_profiling_mask", "mgrit_autotune_scratch_bytes", "mgrit_autotune",
-            "mgrit_cycle_noalloc"]
+            "mgrit_cycle_noalloc", "mgrit_set_tiled_intervals", "mgrit_tiled_intervals"]
 
 # size of the library's static workspace of mgrit_cycle_noalloc (MGRIT_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -419,6 +419,18 @@ def tiled_config(nx: int):
 def set_tiled_config(nx_lo: int, nx_hi: int, cpt: int, waves: int):
     """Split lines of nx_lo..nx_hi cells into tiles of at most 64*waves*cpt cells."""
     _check(load().mgrit_set_tiled_config(nx_lo, nx_hi, cpt, waves))
+
+
+def set_tiled_intervals(nx_lo: int, nx_hi: int, cpt: int, waves: int, intervals: int):
+    """Split lines of nx_lo..nx_hi cells into tiles of (cpt, waves), each
+    workgroup advancing ``intervals`` chunks (1 or 2) together."""
+    _check(load().mgrit_set_tiled_intervals(nx_lo, nx_hi, cpt, waves, intervals))
+
+
+def tiled_intervals(nx: int) -> int:
+    n = C.c_int32(0)
+    _check(load().mgrit_tiled_intervals(nx, C.byref(n)))
+    return n.value
 
 
 def clear_tiled_config():
