@@ -167,19 +167,24 @@ bool tiled_compiled(int cpt, int nw, int intervals = 1)
     return false;
 }
 
+// fewest tiles of configuration c that hold a line of nx cells (balanced in
+// whole threads, mgk::tiles_fit)
 int tiles_for(int nx, const KernelCfg& c)
 {
     const int T = 64 * c.nw * c.cpt;
-    return (nx + T - 1) / T;
+    int G = (nx + T - 1) / T;
+    while (G < nx && !mgk::tiles_fit(nx, G, c.cpt, c.nw)) ++G;
+    return G;
 }
 
 // Configuration and number of tiles for lines of nx cells, or false when a
-// line of nx cells runs in one workgroup.  Default: 4096-cell tiles of 4
-// cells per thread when the line splits into whole threads, else 2048-cell
-// tiles (4 cells per thread, 8 waves), which keep the ragged variant free
-// of register spills.
+// line of nx cells runs in one workgroup.  Default: tiles of whole threads,
+// 4 cells per thread (up to 4096 cells) when 4 divides nx, else 2 cells per
+// thread (up to 2048 cells, 16 waves) when nx is even; odd lines take
+// 2048-cell tiles of 4 cells per thread and 8 waves, whose ragged variant
+// the compiler holds free of register spills.
 // Longest split line: 256 tiles of 4096 cells (one per compute unit), or 512
-// tiles of 2048 cells (two per compute unit).
+// tiles of 2048 cells.
 const int kMaxTiledLine = 1 << 20;
 
 bool choose_tiled(int nx, KernelCfg* out, int* tiles)
@@ -189,17 +194,12 @@ bool choose_tiled(int nx, KernelCfg* out, int* tiles)
         if (nx >= o.nx_lo && nx <= o.nx_hi) {
             *out = o.cfg;
             *tiles = tiles_for(nx, o.cfg);
-            return nx / *tiles >= 3;
+            return mgk::tiles_fit(nx, *tiles, o.cfg.cpt, o.cfg.nw);
         }
     if (nx <= kMaxLine) return false;
-    const KernelCfg big{4, 16};
-    const int G = tiles_for(nx, big);
-    if (nx % G == 0 && (nx / G) % 4 == 0) {
-        *out = big;
-        *tiles = G;
-        return true;
-    }
-    *out = KernelCfg{4, 8};
+    if (nx % 4 == 0) *out = KernelCfg{4, 16};
+    else if (nx % 2 == 0 && nx <= kMaxTiledLine / 2) *out = KernelCfg{2, 16};
+    else *out = KernelCfg{4, 8};
     *tiles = tiles_for(nx, *out);
     return true;
 }
@@ -1520,7 +1520,6 @@ int mgrit_cycle_levels(const mgrit_scheme* schemes, const mgrit_params* p, const
 namespace {
 
 // longest line whose serial solve a batch runs on one workgroup
-const int kMaxBatchSerialLine = 64 * 16 * 8;
 
 struct BatchBucket {
     KernelCfg cfg;
@@ -1528,8 +1527,9 @@ struct BatchBucket {
     int roe;                 // numerical flux of every problem in the bucket
     std::vector<int> probs;  // problem indices
     std::vector<int> offset;
-    int nblocks;
+    int nblocks;             // workgroups (one line each), or work items of split lines
     size_t dev_off;          // offset / problem arrays in the workspace
+    int tiles;               // split lines: workgroups per line (0: one workgroup per line)
 };
 
 struct BatchPhase {
@@ -1583,6 +1583,9 @@ int check_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p
 
 // Record the sweeps of one cycle of every problem, group them into buckets and
 // lay out the workspace.  With ws == nullptr only the sizes are computed.
+// tiles of the serial solves of split-line problems in a batch
+const int kBatchSerialTiles = 4;
+
 int plan_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p, char* ws, BatchPlan* bp)
 {
     bp->count = count;
@@ -1664,15 +1667,23 @@ int plan_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p,
                 KernelCfg c;
                 int t = 0;
                 const bool serial = r.a.nchunks == 1 && r.a.end_mode == mgk::END_NONE;
+                int tiles = 0;
                 if (choose_tiled(probs[i].scheme.nx, &c, &t)) {
-                    if (serial && probs[i].scheme.nx <= kMaxBatchSerialLine) {
-                        // one workgroup of 16 waves x 8 cells: every problem's serial
-                        // solve runs at once instead of one split launch after another
-                        c = KernelCfg{8, 16};
-                    } else {
+                    if (serial && mgk::tiles_fit(probs[i].scheme.nx, kBatchSerialTiles, 2, 16)) {
+                        // serial solves (no residual partials, so any tiling) share one
+                        // shape: every split-line problem's solve runs at once, each on
+                        // 4 tiles, which also shortens its step
+                        c = KernelCfg{2, 16};
+                        t = kBatchSerialTiles;
+                    }
+                    if (!mgk::tiled_batch_compiled(c)) {
+                        // a split shape not compiled for batches: the problem's own launches
                         P.split.push_back(i);
                         continue;
                     }
+                    // every split-line problem of the phase with this shape and tile
+                    // count in one persistent launch
+                    tiles = t;
                 } else {
                     // serial solves (one chunk per problem) take the latency configuration
                     const int nl = serial ? 1 : (int)std::min<long long>(total_lines, 1 << 30);
@@ -1687,9 +1698,10 @@ int plan_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p,
                 const int roe = probs[i].scheme.numflux;
                 BatchBucket* bk = nullptr;
                 for (BatchBucket& b : P.buckets)
-                    if (b.cfg.cpt == c.cpt && b.cfg.nw == c.nw && b.ragged == rag && b.roe == roe) bk = &b;
+                    if (b.cfg.cpt == c.cpt && b.cfg.nw == c.nw && b.ragged == rag && b.roe == roe && b.tiles == tiles)
+                        bk = &b;
                 if (bk == nullptr) {
-                    P.buckets.push_back(BatchBucket{c, rag, roe, {}, {}, 0, 0});
+                    P.buckets.push_back(BatchBucket{c, rag, roe, {}, {}, 0, 0, tiles});
                     bk = &P.buckets.back();
                 }
                 bk->offset.push_back(bk->nblocks);
@@ -1814,11 +1826,21 @@ int mgrit_cycle_batched(const mgrit_problem* probs, int32_t count, const mgrit_p
                         cells += phi * (double)probs[i].scheme.nx;
                     }
                 }
+                t.tiles = b.tiles > 0 ? b.tiles : 1;
+                t.tile_sync = nullptr;
+                t.tile_pub = nullptr;
+                t.groups = 0;
+                if (b.tiles > 0) {
+                    char* scratch = ws + bp.tile_off;
+                    t.tile_sync = (unsigned long long*)scratch;
+                    t.tile_pub = (double*)(scratch + mgk::tile_sync_bytes());
+                }
                 ProfLaunch pl;
                 int prc = pl.begin(P.kc, phi_lines, cells, st);
                 if (prc) return prc;
-                hipError_t e = mgk::launch_batch(t, b.cfg, k0, st0, st);
-                if (e != hipSuccess) return hip_fail(e, "batched sweep kernel launch");
+                hipError_t e = (b.tiles > 0) ? mgk::launch_tiled_batch(t, b.cfg, k0, st0, st)
+                                             : mgk::launch_batch(t, b.cfg, k0, st0, st);
+                if (e != hipSuccess) return hip_fail(e, b.tiles > 0 ? "batched split-line launch" : "batched sweep kernel launch");
                 if ((prc = pl.end(st))) return prc;
             }
             for (int i : P.split) {

@@ -186,6 +186,30 @@ hipError_t launch_reduce_norm_batch(const BatchNorm* tab, int count, double tol,
 template <int K, int ST>
 hipError_t launch_batch_ks(const BatchLaunch& t, const KernelCfg& cfg, hipStream_t s);
 
+template <int K, int ST>
+hipError_t launch_tiled_batch_ks(const BatchLaunch& t, const KernelCfg& cfg, hipStream_t s);
+
+bool tiled_batch_compiled(const KernelCfg& cfg)
+{
+#define MGK_CASE(C, W) \
+    if (cfg.cpt == C && cfg.nw == W && cfg.intervals == 1) return true;
+    MGK_TILED_BATCH_CFG_LIST(MGK_CASE)
+#undef MGK_CASE
+    return false;
+}
+
+// every split-line problem of a batch phase in one launch (degree 0..2)
+hipError_t launch_tiled_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
+{
+    if (t.nblocks <= 0) return hipSuccess;
+    switch (k) {
+    case 0: MGK_DISPATCH_KS(launch_tiled_batch_ks, 0, t, cfg, s);
+    case 1: MGK_DISPATCH_KS(launch_tiled_batch_ks, 1, t, cfg, s);
+    case 2: MGK_DISPATCH_KS(launch_tiled_batch_ks, 2, t, cfg, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
 {
     if (t.nblocks <= 0) return hipSuccess;

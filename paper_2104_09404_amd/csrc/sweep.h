@@ -82,15 +82,22 @@ struct SweepArgs {
 // One batched launch: workgroup b runs chunk b - offset[i] of problem
 // problem[i], i the last bucket entry with offset[i] <= b, with the arguments
 // args[problem[i]] (device memory).
+// A split-line batch launch reads the same table as (problem, chunk) work
+// items: line groups of `tiles` workgroups take items grp, grp + groups, ...
+// and synchronise through tile_sync / tile_pub.
 struct BatchLaunch {
     const SweepArgs* args;
     const int* offset;   // nprob entries, ascending, offset[0] = 0
     const int* problem;  // nprob entries
     int nprob;
-    int nblocks;
+    int nblocks;         // work items (chunks of all problems of the launch)
     int end_mode;        // END_NONE, END_CSTEP or END_RESTRICT (every entry of args has it)
     int ragged;          // some problem's line is not a multiple of the cells per thread
     int roe;             // every problem of the launch uses the Roe flux (else LF)
+    int tiles;           // split lines: workgroups per line (else 1)
+    unsigned long long* tile_sync;  // split lines: error word
+    double* tile_pub;               // split lines: published slots
+    int groups;          // split lines: line groups of the launch (set at launch)
     int pad_;
 };
 
@@ -208,10 +215,17 @@ struct KernelCfg {
 #define MGK_TILED_PAIR_CFG_LIST(X) \
     X(4, 8)
 
+// split-line shapes compiled for batches (the default choices of split lines)
+#define MGK_TILED_BATCH_CFG_LIST(X) \
+    X(4, 16)                        \
+    X(2, 16)                        \
+    X(4, 8)
+
 #define MGK_TILED_CFG_LIST(X) \
     X(1, 4)                   \
     X(2, 4)                   \
     X(2, 8)                   \
+    X(2, 16)                  \
     X(4, 4)                   \
     X(4, 8)                   \
     X(4, 16)
@@ -223,6 +237,18 @@ struct KernelCfg {
     X(2, 4)                  \
     X(1, 8)                  \
     X(2, 8)
+
+// Split lines: G tiles balanced in whole threads (TGeo) of at least 3 and at
+// most 64 nw cpt cells each.  The shortest tile holds cpt floor(U/G) cells and
+// the longest cpt ceil(U/G) + nx mod cpt, U = floor(nx / cpt).
+inline bool tiles_fit(int64_t nx, int64_t G, int cpt, int nw)
+{
+    if (G < 1 || cpt < 1) return false;
+    const int64_t U = nx / cpt;
+    const int64_t shortest = (int64_t)cpt * (U / G);
+    const int64_t longest = (int64_t)cpt * ((U + G - 1) / G) + nx % cpt;
+    return shortest >= 3 && longest <= 64 * (int64_t)nw * cpt;
+}
 
 inline size_t tiled_smem_bytes(int cpt, int nw)
 {
@@ -237,6 +263,8 @@ inline size_t smem_bytes(int cpt, int nw)
 hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
 hipError_t launch_tiled(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
 hipError_t launch_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
+hipError_t launch_tiled_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
+bool tiled_batch_compiled(const KernelCfg& cfg);
 hipError_t launch_reduce_norm_batch(const BatchNorm* tab, int count, double tol, int* converged, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int stepper, int store_mode, hipStream_t s);
 hipError_t launch_tiled_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int stepper, int store_mode,

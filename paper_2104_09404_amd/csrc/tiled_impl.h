@@ -65,10 +65,12 @@ struct TSmem {
     }
 };
 
-// Tiles have balanced lengths: tile g covers cells floor(g nx / G) ..
-// floor((g+1) nx / G) - 1 (at most 64 NW CPT cells, at least 3).  Thread t
-// owns tile cells t CPT .. t CPT + CPT - 1; the last active thread may own
-// fewer (ragged).
+// Tiles have balanced lengths in whole threads: with U = floor(nx / CPT),
+// tile g covers cells CPT floor(g U / G) .. CPT floor((g+1) U / G) - 1, the
+// last tile also the nx mod CPT cells left over (at most 64 NW CPT cells, at
+// least 3).  Thread t owns tile cells t CPT .. t CPT + CPT - 1; only the last
+// tile's last active thread may own fewer (ragged), and only when CPT does
+// not divide nx.
 template <int CPT, int NW>
 struct TGeo {
     int64_t x0;     // first cell of the tile in the line
@@ -96,8 +98,9 @@ struct TGeo {
 
     __device__ __forceinline__ void init(int64_t nx, int tile, int G)
     {
-        x0 = (int64_t)tile * nx / G;
-        Tv = (int)((int64_t)(tile + 1) * nx / G - x0);
+        const int64_t units = nx / CPT;  // whole threads' worth of cells
+        x0 = (int64_t)CPT * ((int64_t)tile * units / G);
+        Tv = (tile == G - 1) ? (int)(nx - x0) : (int)((int64_t)CPT * ((int64_t)(tile + 1) * units / G) - x0);
         t = threadIdx.x;
         j0 = t * CPT;
         active = j0 < Tv;
@@ -917,6 +920,68 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MGK_TIL
 }
 
 // ---------------------------------------------------------------------------
+// batches: every split-line problem of a phase in one persistent launch
+// ---------------------------------------------------------------------------
+// Work items are the (problem, chunk) pairs of the launch's table, problem i
+// owning items offset[i] .. offset[i+1] - 1.  Line group grp (workgroups
+// grp G .. grp G + G - 1) takes items grp, grp + groups, ...  Each item runs
+// exactly tiled_chunk on its problem's arguments, with the problem's own
+// tile geometry; the group's slot ring simply continues from item to item.
+// A problem whose stop flag is set (it converged) contributes no work.
+template <int CPT, int NW, int K, int ST, bool RAG, int END, bool ROE>
+__device__ __forceinline__ void tiled_batch_body(const BatchLaunch& t)
+{
+    extern __shared__ double smem_raw[];
+    TSmem<CPT, NW> sm;
+    sm.init(smem_raw);
+    const int G = t.tiles;
+    const int tile = blockIdx.x % G;
+    const int grp = blockIdx.x / G;
+    TSync ts;
+    ts.cnt = nullptr;
+    ts.ring = kTileRing;
+    ts.err = t.tile_sync;
+    ts.pub = t.tile_pub + (int64_t)grp * G * kTileRing * kTileSlot;
+    ts.G = G;
+    ts.tile = tile;
+    ts.ep = 0;
+    for (int j = grp; j < t.nblocks; j += t.groups) {
+        int lo = 0, hi = t.nprob - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (t.offset[mid] <= j) lo = mid;
+            else hi = mid - 1;
+        }
+        const SweepArgs a = t.args[t.problem[lo]];
+        if (a.flag != nullptr && *a.flag != 0) continue;
+        TGeo<CPT, NW> g;
+        g.init(a.nx, tile, G);
+        if (!tiled_chunk<CPT, NW, K, ST, RAG, END, ROE>(a, j - t.offset[lo], g, sm, ts)) return;
+    }
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(RAG ? 1 : 4))) void tiled_batch_f_kernel(
+    BatchLaunch t)
+{
+    tiled_batch_body<CPT, NW, K, ST, RAG, END_NONE, ROE>(t);
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(RAG ? 1 : 4))) void tiled_batch_fc_kernel(
+    BatchLaunch t)
+{
+    tiled_batch_body<CPT, NW, K, ST, RAG, END_CSTEP, ROE>(t);
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(RAG ? 1 : 4))) void tiled_batch_fr_kernel(
+    BatchLaunch t)
+{
+    tiled_batch_body<CPT, NW, K, ST, RAG, END_RESTRICT, ROE>(t);
+}
+
+// ---------------------------------------------------------------------------
 // cooperative, persistent launch
 // ---------------------------------------------------------------------------
 template <class Fn>
@@ -969,14 +1034,14 @@ static hipError_t launch_tiled_role(const SweepArgs& a, hipStream_t s)
     return launch_tiled_role_f<CPT, NW, K, ST, RAG, false, PAIR>(a, s);
 }
 
-// The tile lengths (balanced, see TGeo) must lie in [3, 64 NW CPT]; the
-// launch is ragged unless every tile is a whole number of threads.
+// The tile lengths (balanced in whole threads, see TGeo) must lie in
+// [3, 64 NW CPT]; the launch is ragged unless CPT divides nx.
 template <int CPT, int NW, int K, int ST, bool PAIR>
 static hipError_t launch_tiled_cfg(const SweepArgs& a, hipStream_t s)
 {
     const int64_t nx = a.nx, G = a.tiles;
-    if (G < 1 || nx / G < 3 || (nx + G - 1) / G > 64 * NW * CPT) return hipErrorInvalidValue;
-    if (nx % G == 0 && (nx / G) % CPT == 0) return launch_tiled_role<CPT, NW, K, ST, false, PAIR>(a, s);
+    if (!tiles_fit(nx, G, CPT, NW)) return hipErrorInvalidValue;
+    if (nx % CPT == 0) return launch_tiled_role<CPT, NW, K, ST, false, PAIR>(a, s);
     return launch_tiled_role<CPT, NW, K, ST, true, PAIR>(a, s);
 }
 
@@ -990,6 +1055,69 @@ hipError_t launch_tiled_ks(const SweepArgs& a, const KernelCfg& cfg, hipStream_t
 #define MGK_CASE(C, W) \
     if (cfg.cpt == C && cfg.nw == W && cfg.intervals == 2) return launch_tiled_cfg<C, W, K, ST, true>(a, s);
     MGK_TILED_PAIR_CFG_LIST(MGK_CASE)
+#undef MGK_CASE
+    return hipErrorInvalidValue;
+}
+
+// every split-line problem of a batch phase (same shape and tile count) in
+// one cooperative, persistent launch
+template <class Fn>
+static hipError_t launch_coop_batch(Fn fn, const BatchLaunch& t, int nw, size_t shmem, hipStream_t s)
+{
+    hipError_t e;
+    if (shmem > 65536) {
+        e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    int dev = 0, ncu = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, 64 * nw, shmem)) != hipSuccess)
+        return e;
+    const long long cap = std::min((long long)per_cu * ncu, (long long)kTileMaxWorkgroups);
+    const int G = t.tiles;
+    if (G < 1 || cap < G) return hipErrorCooperativeLaunchTooLarge;
+    BatchLaunch b = t;
+    b.groups = (int)std::min((long long)t.nblocks, cap / G);
+    e = launch_clear_ints((int*)b.tile_sync, 2, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u64((unsigned long long*)b.tile_pub, kSlotEmpty, (int64_t)b.groups * G * kTileRing * kTileSlot, s);
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)&b};
+    return hipLaunchCooperativeKernel((const void*)fn, dim3((unsigned)(b.groups * G)), dim3(64 * nw), args,
+                                      (unsigned)shmem, s);
+}
+
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
+static hipError_t launch_tiled_batch_role(const BatchLaunch& t, hipStream_t s)
+{
+    const size_t shmem = tiled_smem_bytes(CPT, NW);
+    switch (t.end_mode) {
+    case END_NONE: return launch_coop_batch(tiled_batch_f_kernel<CPT, NW, K, ST, RAG, ROE>, t, NW, shmem, s);
+    case END_CSTEP: return launch_coop_batch(tiled_batch_fc_kernel<CPT, NW, K, ST, RAG, ROE>, t, NW, shmem, s);
+    case END_RESTRICT: return launch_coop_batch(tiled_batch_fr_kernel<CPT, NW, K, ST, RAG, ROE>, t, NW, shmem, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int CPT, int NW, int K, int ST>
+static hipError_t launch_tiled_batch_cfg(const BatchLaunch& t, hipStream_t s)
+{
+    if (t.ragged) {
+        if (t.roe) return launch_tiled_batch_role<CPT, NW, K, ST, true, true>(t, s);
+        return launch_tiled_batch_role<CPT, NW, K, ST, true, false>(t, s);
+    }
+    if (t.roe) return launch_tiled_batch_role<CPT, NW, K, ST, false, true>(t, s);
+    return launch_tiled_batch_role<CPT, NW, K, ST, false, false>(t, s);
+}
+
+template <int K, int ST>
+hipError_t launch_tiled_batch_ks(const BatchLaunch& t, const KernelCfg& cfg, hipStream_t s)
+{
+    if (t.nblocks <= 0) return hipSuccess;
+#define MGK_CASE(C, W) \
+    if (cfg.cpt == C && cfg.nw == W && cfg.intervals == 1) return launch_tiled_batch_cfg<C, W, K, ST>(t, s);
+    MGK_TILED_BATCH_CFG_LIST(MGK_CASE)
 #undef MGK_CASE
     return hipErrorInvalidValue;
 }

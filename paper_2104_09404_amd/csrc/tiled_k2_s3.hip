@@ -5,4 +5,5 @@
 
 namespace mgk {
 template hipError_t launch_tiled_ks<2, 3>(const SweepArgs& a, const KernelCfg& cfg, hipStream_t s);
+template hipError_t launch_tiled_batch_ks<2, 3>(const BatchLaunch& t, const KernelCfg& cfg, hipStream_t s);
 }  // namespace mgk
