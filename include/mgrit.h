@@ -427,6 +427,27 @@ int mgrit_autotune(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, void* 
                    int32_t install, int32_t* cells_per_thread, int32_t* waves, float* ms_best, void* stream);
 
 /*
+ * Split-line autotuner (not in the paper): times nsteps applications of Phi
+ * on nlines lines of s->nx cells for every compiled split-line shape (cells
+ * per thread, waves per tile, and intervals per workgroup: one chunk, or two
+ * chunks advanced half a stage apart) whose balanced tiles hold the line and
+ * can all be resident at once, and picks the fastest (median of three
+ * launches after one warm-up, HIP events on `stream`).  With install != 0 the
+ * choice becomes the split-line setting for lines of exactly s->nx cells, as
+ * mgrit_set_tiled_intervals would set it.  Every shape evaluates the same
+ * per-cell operations, so results do not depend on the choice.
+ *   scratch  device, at least mgrit_autotune_scratch_bytes(s->nx, nlines)
+ *            bytes, caller-owned; overwritten with smooth test lines.
+ *   cells_per_thread, waves, intervals, ms_best  HOST outputs (may be NULL).
+ * Synchronises the stream; uses (and on first use allocates) the device's
+ * split-line synchronisation buffer.  Systems and WENO7 (k = 3) return
+ * MGRIT_EUNSUPPORTED.  Not thread safe when installing.
+ */
+int mgrit_autotune_tiled(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, void* scratch, size_t scratch_bytes,
+                         int32_t install, int32_t* cells_per_thread, int32_t* waves, int32_t* intervals,
+                         float* ms_best, void* stream);
+
+/*
  * Batches of independent problems (many initial-value problems solved by
  * MGRIT together; not in the paper).  Every problem has its own scheme
  * constants (flux, advection speed, nx, eps, L, alpha_fixed), fine step count

@@ -965,6 +965,87 @@ int mgrit_autotune(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, void* 
     return MGRIT_OK;
 }
 
+int mgrit_autotune_tiled(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, void* scratch, size_t scratch_bytes,
+                         int32_t install, int32_t* cells_per_thread, int32_t* waves, int32_t* intervals,
+                         float* ms_best, void* stream)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if (is_system(s)) return fail(MGRIT_EUNSUPPORTED, "systems do not run on split lines");
+    if (s->k == 3) return fail(MGRIT_EUNSUPPORTED, "WENO7 (k = 3) does not run on split lines");
+    if (nlines < 1 || nsteps < 1) return fail(MGRIT_EINVAL, "nlines and nsteps must be >= 1");
+    if (scratch == nullptr || scratch_bytes < mgrit_autotune_scratch_bytes(s->nx, nlines))
+        return fail(MGRIT_EINVAL, "scratch must hold nlines x nx doubles");
+    char* tscratch = nullptr;
+    if ((rc = device_tile_scratch(&tscratch))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    double* lines = (double*)scratch;
+    HIP_TRY(mgk::launch_fill_wave(lines, s->nx, nlines, st), "fill kernel launch");
+    const double dx = s->L / (double)s->nx;
+    const double speed = (s->flux == 0) ? 0.75 : (std::fabs(s->a) > 0.0 ? std::fabs(s->a) : 1.0);
+    const double dt = 0.5 * dx / speed;
+    SweepArgs a = base_args(s);
+    a.nchunks = nlines;
+    a.m = 0;
+    a.nsteps = nsteps;
+    a.end_mode = mgk::END_NONE;
+    a.dt = dt;
+    a.ustart = lines;
+    a.ustart_stride = 1;  // nothing is stored: the lines stay as filled
+    a.pc = phi_const(s, dt);
+    a.tile_sync = (unsigned long long*)tscratch;
+    a.tile_pub = (double*)(tscratch + mgk::tile_sync_bytes());
+    std::vector<KernelCfg> cands(std::begin(kTiledCfgs), std::end(kTiledCfgs));
+    cands.insert(cands.end(), std::begin(kTiledPairCfgs), std::end(kTiledPairCfgs));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    float best = -1.f;
+    KernelCfg best_cfg{0, 0};
+    for (const KernelCfg& c : cands) {
+        const int G = tiles_for(s->nx, c);
+        if (!mgk::tiles_fit(s->nx, G, c.cpt, c.nw) || G > 256) continue;
+        a.tiles = G;
+        float t[3] = {0.f, 0.f, 0.f};
+        bool fits = true;
+        for (int r = 0; r < 4 && rc == MGRIT_OK && fits; ++r) {  // one warm-up, three timed
+            hipError_t e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = mgk::launch_tiled(a, c, s->k, s->stepper, st);
+            if (e == hipErrorCooperativeLaunchTooLarge) {  // the tiles of a line cannot be resident at once
+                fits = false;
+                break;
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) rc = hip_fail(e, "autotune launch");
+            else if (r > 0) t[r - 1] = ms;
+        }
+        if (rc) break;
+        if (!fits) continue;
+        std::sort(t, t + 3);
+        if (best < 0.f || t[1] < best) {
+            best = t[1];
+            best_cfg = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    unsigned long long w = 0;
+    HIP_TRY(hipMemcpy(&w, tscratch, sizeof(w), hipMemcpyDeviceToHost), "hipMemcpy");
+    if (w != 0) return fail(MGRIT_EHIP, "split-line autotune: workgroups of a line failed to synchronise");
+    if (best < 0.f) return fail(MGRIT_EUNSUPPORTED, "no split-line configuration holds nx = %d", s->nx);
+    if (install)
+        g_tiled_overrides.insert(g_tiled_overrides.begin(), TiledOverride{s->nx, s->nx, best_cfg});
+    if (cells_per_thread) *cells_per_thread = best_cfg.cpt;
+    if (waves) *waves = best_cfg.nw;
+    if (intervals) *intervals = best_cfg.intervals;
+    if (ms_best) *ms_best = best;
+    return MGRIT_OK;
+}
+
 int mgrit_tiled_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves, int32_t* tiles)
 {
     KernelCfg c{0, 0};

@@ -29,7 +29,7 @@ EXPORTED = ["mgrit_phi", "mgrit_serial", "mgrit_relax", "mgrit_residual", "mgrit
             "mgrit_adjoint_workspace_bytes", "mgrit_adjoint", "mgrit_tiled_config", "mgrit_set_tiled_config",
             "mgrit_batched_workspace_bytes", "mgrit_cycle_batched", "mgrit_cycle_levels",
             "mgrit_set_profiling_mask", "mgrit_autotune_scratch_bytes", "mgrit_autotune",
-            "mgrit_cycle_noalloc", "mgrit_set_tiled_intervals", "mgrit_tiled_intervals"]
+            "mgrit_cycle_noalloc", "mgrit_set_tiled_intervals", "mgrit_tiled_intervals", "mgrit_autotune_tiled"]
 
 # size of the library's static workspace of mgrit_cycle_noalloc (MGRIT_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -131,6 +131,8 @@ def load(path: str = LIB_PATH):
     L.mgrit_autotune_scratch_bytes.restype = C.c_size_t
     L.mgrit_autotune.argtypes = [S, i32, i32, vp, C.c_size_t, i32, C.POINTER(i32), C.POINTER(i32),
                                  C.POINTER(C.c_float), vp]
+    L.mgrit_autotune_tiled.argtypes = [S, i32, i32, vp, C.c_size_t, i32, C.POINTER(i32), C.POINTER(i32),
+                                       C.POINTER(i32), C.POINTER(C.c_float), vp]
     L.mgrit_set_profiling_mask.argtypes = [C.c_uint32]
     L.mgrit_set_profiling_mask.restype = None
     L.mgrit_get_profile.argtypes = [C.POINTER(ProfileEntry), C.c_int]
@@ -321,6 +323,22 @@ def autotune(s: Scheme, nlines: int, nsteps: int = 8, install: bool = True, stre
     _check(load().mgrit_autotune(C.byref(s), nlines, nsteps, C.c_void_p(scratch.data_ptr()), n, 1 if install else 0,
                                  C.byref(cpt), C.byref(nw), C.byref(ms), _stream(stream)))
     return cpt.value, nw.value, ms.value
+
+
+def autotune_tiled(s: Scheme, nlines: int, nsteps: int = 4, install: bool = True, stream=None):
+    """Time every compiled split-line shape (cells per thread, waves, intervals
+    per workgroup) on nlines lines of s.nx cells and (install) make the
+    fastest the setting for that line length; returns (cpt, waves,
+    intervals, ms)."""
+    import torch
+
+    nbytes = load().mgrit_autotune_scratch_bytes(s.nx, nlines)
+    scratch = torch.empty(nbytes // 8 + 1, dtype=torch.float64, device="cuda")
+    c, w, iv, ms = C.c_int32(0), C.c_int32(0), C.c_int32(0), C.c_float(0.0)
+    _check(load().mgrit_autotune_tiled(C.byref(s), nlines, nsteps, C.c_void_p(scratch.data_ptr()), nbytes,
+                                       1 if install else 0, C.byref(c), C.byref(w), C.byref(iv), C.byref(ms),
+                                       _stream(stream)))
+    return c.value, w.value, iv.value, ms.value
 
 
 def autotune_batch(problems, nsteps: int = 8, stream=None) -> dict:

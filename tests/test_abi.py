@@ -226,3 +226,18 @@ def test_noalloc_refuses_oversized_problem_without_gpu(lib):
     assert mgrit.NOALLOC_SCRATCH_BYTES == 64 << 20
     text = open(HEADER).read()
     assert "#define MGRIT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)" in text
+
+
+def test_split_autotune_validation_without_gpu(lib):
+    """The split-line autotuner checks its arguments on the host."""
+    from paper_2104_09404_amd import mgrit
+
+    s = mgrit.scheme(8192)
+    n = C.c_int32(0)
+    args = (None, None, None, None, None)
+    assert lib.mgrit_autotune_tiled(C.byref(s), 64, 2, None, 0, 1, *args) == mgrit.MGRIT_EINVAL
+    assert b"scratch" in lib.mgrit_last_error()
+    assert lib.mgrit_autotune_tiled(C.byref(mgrit.euler_scheme(64)), 64, 2, None, 0, 1, *args) == mgrit.MGRIT_EUNSUPPORTED
+    assert lib.mgrit_autotune_tiled(C.byref(mgrit.scheme(8192, k=3)), 64, 2, None, 0, 1, *args) == mgrit.MGRIT_EUNSUPPORTED
+    assert lib.mgrit_autotune_tiled(C.byref(s), 0, 2, None, 0, 1, *args) == mgrit.MGRIT_EINVAL
+    assert n.value == 0

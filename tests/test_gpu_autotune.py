@@ -82,3 +82,26 @@ def test_autotuned_batch_equals_untuned(gpu):
     for a, b in zip(ref, got):
         with np.errstate(invalid="ignore"):
             assert np.all((a == b) | (np.isnan(a) & np.isnan(b)))
+
+
+@pytest.mark.parametrize("nx,nlines", [(8192, 64), (6002, 64), (65536, 16)])
+def test_split_line_autotune(gpu, nx, nlines):
+    """mgrit_autotune_tiled times every compiled split-line shape, including
+    two intervals (chunks) per workgroup, installs the fastest, and results
+    stay bitwise equal."""
+    s = gpu.scheme(nx)
+    u = W.random_lines(19, 4, nx)
+    dt = 0.5 / nx / np.max(np.abs(u))
+    before = T(np.zeros_like(u))
+    gpu.phi(s, dt, T(u), before)
+    try:
+        cpt, nw, iv, ms = gpu.autotune_tiled(s, nlines, 2)
+        assert ms > 0.0 and iv in (1, 2)
+        tc = gpu.tiled_config(nx)
+        assert tc[:2] == (cpt, nw) and tc[2] >= 1
+        assert gpu.tiled_intervals(nx) == iv
+        after = T(np.zeros_like(u))
+        gpu.phi(s, dt, T(u), after)
+        assert np.array_equal(H(before), H(after))
+    finally:
+        gpu.clear_tiled_config()
