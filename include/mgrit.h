@@ -11,7 +11,7 @@
  *   - All array pointers are DEVICE pointers to contiguous FP64 data owned by
  *     the caller (e.g. torch tensors).  The library never allocates or frees
  *     caller memory.  It allocates device memory only once per device: the
- *     4.2 MB synchronisation buffer of split lines (below), on the first
+ *     10.5 MB synchronisation buffer of split lines (below), on the first
  *     split-line launch outside mgrit_cycle, kept until the process ends.
  *   - Line length.  Lines of up to 4096 cells run on one workgroup each.
  *     Longer lines (or any range chosen with mgrit_set_tiled_config) are split
@@ -82,8 +82,8 @@ enum {
  *            2 = WENO5-JS with the printed k = 2 tables; 3 = WENO7.  Stencil
  *            r = {i-r, ..., i-r+k}; for k = 1 and 3 the tables of eq C, B and D
  *            are those their definitions give (the paper prints k = 2 only).
- *            k = 3 runs on lines of at most 4096 cells (else
- *            MGRIT_EUNSUPPORTED).
+ *            Split lines keep k + 1 ghost cells per tile side for k = 3
+ *            (3 otherwise).
  *   stepper  1: forward Euler (eq SSPRK1); 2: SSPRK2; 3: SSPRK3 (eq SSPRK3).
  *   nx       number of cells N_x >= 8.
  *   a        flux parameter: advection speed (flux 1), g (flux 2), gamma (flux 3).
@@ -440,8 +440,8 @@ int mgrit_autotune(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, void* 
  *            bytes, caller-owned; overwritten with smooth test lines.
  *   cells_per_thread, waves, intervals, ms_best  HOST outputs (may be NULL).
  * Synchronises the stream; uses (and on first use allocates) the device's
- * split-line synchronisation buffer.  Systems and WENO7 (k = 3) return
- * MGRIT_EUNSUPPORTED.  Not thread safe when installing.
+ * split-line synchronisation buffer.  Systems return MGRIT_EUNSUPPORTED.
+ * Not thread safe when installing.
  */
 int mgrit_autotune_tiled(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, void* scratch, size_t scratch_bytes,
                          int32_t install, int32_t* cells_per_thread, int32_t* waves, int32_t* intervals,

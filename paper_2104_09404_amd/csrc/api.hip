@@ -318,9 +318,6 @@ int check_scheme(const mgrit_scheme* s)
     const bool split = choose_tiled(s->nx, &c, &tiles);
     if (!split && !choose_cfg(s->nx, kLatencyLines, &c))
         return fail(MGRIT_EUNSUPPORTED, "no kernel configuration for nx = %d", s->nx);
-    if (split && s->k == 3)
-        return fail(MGRIT_EUNSUPPORTED, "WENO7 (k = 3) runs on lines of one workgroup (at most %d cells), nx = %d",
-                    kMaxLine, s->nx);
     return MGRIT_OK;
 }
 
@@ -460,7 +457,6 @@ int launch(int kc, const SweepArgs& a_in, const mgrit_scheme* s, hipStream_t st,
         return pl.end(st);
     }
     const bool tiled = choose_tiled(s->nx, &cfg, &tiles);
-    if (tiled && s->k == 3) return fail(MGRIT_EUNSUPPORTED, "WENO7 (k = 3) does not run on split lines");
     if (tiled && (a0.coarse_split || a0.gc_sub != nullptr))
         return fail(MGRIT_EUNSUPPORTED, "a scheme per level does not run on split lines");
     if (tiled) {
@@ -972,7 +968,6 @@ int mgrit_autotune_tiled(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, 
     int rc = check_scheme(s);
     if (rc) return rc;
     if (is_system(s)) return fail(MGRIT_EUNSUPPORTED, "systems do not run on split lines");
-    if (s->k == 3) return fail(MGRIT_EUNSUPPORTED, "WENO7 (k = 3) does not run on split lines");
     if (nlines < 1 || nsteps < 1) return fail(MGRIT_EINVAL, "nlines and nsteps must be >= 1");
     if (scratch == nullptr || scratch_bytes < mgrit_autotune_scratch_bytes(s->nx, nlines))
         return fail(MGRIT_EINVAL, "scratch must hold nlines x nx doubles");

@@ -86,7 +86,7 @@ hipError_t launch_sys(const SweepArgs& a, int threads, int flux, int k, int step
     return hipErrorInvalidValue;
 }
 
-// split lines keep three ghost cells per side: WENO degree 0, 1 or 2
+// split lines: WENO degree 0 .. 3 (3 or 4 ghost cells per side)
 hipError_t launch_tiled(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
 {
     if (a.nchunks <= 0) return hipSuccess;
@@ -94,6 +94,7 @@ hipError_t launch_tiled(const SweepArgs& a, const KernelCfg& cfg, int k, int ste
     case 0: MGK_DISPATCH_KS(launch_tiled_ks, 0, a, cfg, s);
     case 1: MGK_DISPATCH_KS(launch_tiled_ks, 1, a, cfg, s);
     case 2: MGK_DISPATCH_KS(launch_tiled_ks, 2, a, cfg, s);
+    case 3: MGK_DISPATCH_KS(launch_tiled_ks, 3, a, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -198,7 +199,7 @@ bool tiled_batch_compiled(const KernelCfg& cfg)
     return false;
 }
 
-// every split-line problem of a batch phase in one launch (degree 0..2)
+// every split-line problem of a batch phase in one launch (degree 0..3)
 hipError_t launch_tiled_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
 {
     if (t.nblocks <= 0) return hipSuccess;
@@ -206,6 +207,7 @@ hipError_t launch_tiled_batch(const BatchLaunch& t, const KernelCfg& cfg, int k,
     case 0: MGK_DISPATCH_KS(launch_tiled_batch_ks, 0, t, cfg, s);
     case 1: MGK_DISPATCH_KS(launch_tiled_batch_ks, 1, t, cfg, s);
     case 2: MGK_DISPATCH_KS(launch_tiled_batch_ks, 2, t, cfg, s);
+    case 3: MGK_DISPATCH_KS(launch_tiled_batch_ks, 3, t, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }

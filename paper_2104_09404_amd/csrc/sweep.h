@@ -114,7 +114,7 @@ struct BatchNorm {
 // tiled lines: doubles per published slot, words between arrival counters
 // (one 128-byte line each, so that groups do not contend for a line), and the
 // largest resident grid the synchronisation scratch is sized for
-constexpr int kTileSlot = 16;
+constexpr int kTileSlot = 24;  // at least 1 + 4 x (ghost cells per side)
 constexpr int kTileCounterStride = 16;
 constexpr int kTileMaxWorkgroups = 8192;
 // forward split-line sweeps publish into a ring of 3 slots per tile (the
@@ -238,7 +238,7 @@ struct KernelCfg {
     X(1, 8)                  \
     X(2, 8)
 
-// Split lines: G tiles balanced in whole threads (TGeo) of at least 3 and at
+// Split lines: G tiles balanced in whole threads (TGeo) of at least 4 and at
 // most 64 nw cpt cells each.  The shortest tile holds cpt floor(U/G) cells and
 // the longest cpt ceil(U/G) + nx mod cpt, U = floor(nx / cpt).
 inline bool tiles_fit(int64_t nx, int64_t G, int cpt, int nw)
@@ -247,12 +247,13 @@ inline bool tiles_fit(int64_t nx, int64_t G, int cpt, int nw)
     const int64_t U = nx / cpt;
     const int64_t shortest = (int64_t)cpt * (U / G);
     const int64_t longest = (int64_t)cpt * ((U + G - 1) / G) + nx % cpt;
-    return shortest >= 3 && longest <= 64 * (int64_t)nw * cpt;
+    return shortest >= 4 && longest <= 64 * (int64_t)nw * cpt;
 }
 
 inline size_t tiled_smem_bytes(int cpt, int nw)
 {
-    return sizeof(double) * (64 * (size_t)nw * (size_t)cpt + 7 + 2 * 64 * (size_t)nw + (size_t)nw + 2 * 40);
+    // tile + 4 ghost cells per side and a scratch slot (degree 3; fewer ghosts otherwise)
+    return sizeof(double) * (64 * (size_t)nw * (size_t)cpt + 9 + 2 * 64 * (size_t)nw + (size_t)nw + 2 * 40);
 }
 
 inline size_t smem_bytes(int cpt, int nw)

@@ -37,15 +37,26 @@ namespace mgk {
 
 constexpr long long kTileSpinLimit = 1LL << 22;
 
-// LDS: tl[T + 7] | bm[64 NW] | bp[64 NW] | amax[NW] | misc[40] | misc2[40]
+// Ghost cells per tile side: the reconstruction of degree K in a cell reads
+// K + 1 cells on each side of it, and a tile reconstructs one cell beyond
+// each of its edges, so degree 3 (WENO7) needs 4, lower degrees 3.
+template <int K>
+constexpr int tile_ghosts()
+{
+    return K == 3 ? 4 : 3;
+}
+
+// LDS: tl[T + 2 NG + 1] | bm[64 NW] | bp[64 NW] | amax[NW] | misc[40] | misc2[40]
 //   tl: the tile's cells transposed (cell c at (c mod CPT) * threads + c / CPT,
 //   so that every window position is read lane-contiguously, free of bank
-//   conflicts), ghost cells -3..-1 at T..T+2 and Tv..Tv+2 at T+3..T+5, one
-//   scratch slot at T+6 for window positions past the ghosts
+//   conflicts), ghost cells -NG..-1 at T..T+NG-1 and Tv..Tv+NG-1 at
+//   T+NG..T+2NG-1, one scratch slot at T+2NG for window positions past the
+//   ghosts (NG ghost cells per side, tile_ghosts)
 //   misc[0] alpha_LF, [1..2] (Fa, Fb) of the tile's left edge interface,
-//   [3..4] of its right edge interface, [5..10] the left neighbour's
-//   right-edge data, [11..16] the right neighbour's left-edge data,
-//   [39] error flag; misc2 the same for the second chunk of a paired sweep
+//   [3..4] of its right edge interface, [5..5+2NG-1] the left neighbour's
+//   right-edge data (NG Fa, then NG Fb), [5+2NG..5+4NG-1] the right
+//   neighbour's left-edge data, [39] error flag; misc2 the same for the second
+//   chunk of a paired sweep
 template <int CPT, int NW>
 struct TSmem {
     double* tl;
@@ -54,10 +65,11 @@ struct TSmem {
     double* amax;
     double* misc;
     double* misc2;
+    template <int NG = 3>
     __device__ __forceinline__ void init(double* base)
     {
         tl = base;
-        bm = tl + 64 * NW * CPT + 7;
+        bm = tl + 64 * NW * CPT + 2 * NG + 1;
         bp = bm + 64 * NW;
         amax = bp + 64 * NW;
         misc = amax + NW;
@@ -68,7 +80,7 @@ struct TSmem {
 // Tiles have balanced lengths in whole threads: with U = floor(nx / CPT),
 // tile g covers cells CPT floor(g U / G) .. CPT floor((g+1) U / G) - 1, the
 // last tile also the nx mod CPT cells left over (at most 64 NW CPT cells, at
-// least 3).  Thread t owns tile cells t CPT .. t CPT + CPT - 1; only the last
+// least 4).  Thread t owns tile cells t CPT .. t CPT + CPT - 1; only the last
 // tile's last active thread may own fewer (ragged), and only when CPT does
 // not divide nx.
 template <int CPT, int NW>
@@ -80,24 +92,27 @@ struct TGeo {
     int Tv;         // cells in this tile
     int tlast;      // thread owning the tile's last cell
     bool active;    // owns cells
-    int gk;         // ghost handled by this thread: 0..2 left, 3..5 right, -1 none
+    int ng;         // ghost cells per side
+    int gk;         // ghost handled by this thread: 0..ng-1 left, ng..2ng-1 right, -1 none
     int gpos;       // LDS position of that ghost
     int64_t gcell;  // its cell in the line (periodic)
-    int halo[6];    // LDS slots of window positions 0..2 and CPT+3..CPT+5
+    int halo[8];    // LDS slots of window positions 0..ng-1 and CPT+ng..CPT+2ng-1
 
-    // LDS slot of tile cell c, -3 <= c (see TSmem)
+    // LDS slot of tile cell c, -ng <= c (see TSmem)
     __device__ __forceinline__ int tslot(int c) const
     {
         const int T = 64 * NW * CPT;
-        if (c < 0) return T + 3 + c;
+        if (c < 0) return T + ng + c;
         if (c < Tv) return (c % CPT) * (64 * NW) + c / CPT;
-        if (c < Tv + 3) return T + 3 + (c - Tv);
-        return T + 6;
+        if (c < Tv + ng) return T + ng + (c - Tv);
+        return T + 2 * ng;
     }
     __device__ __forceinline__ int own(int q) const { return q * (64 * NW) + t; }
 
+    template <int NG = 3>
     __device__ __forceinline__ void init(int64_t nx, int tile, int G)
     {
+        ng = NG;
         const int64_t units = nx / CPT;  // whole threads' worth of cells
         x0 = (int64_t)CPT * ((int64_t)tile * units / G);
         Tv = (tile == G - 1) ? (int)(nx - x0) : (int)((int64_t)CPT * ((int64_t)(tile + 1) * units / G) - x0);
@@ -106,21 +121,21 @@ struct TGeo {
         active = j0 < Tv;
         nvalid = active ? min(CPT, Tv - j0) : 0;
         tlast = (Tv - 1) / CPT;
-        gk = (t < 6) ? t : -1;
+        gk = (t < 2 * NG) ? t : -1;
         gpos = 0;
         gcell = 0;
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            halo[p] = active ? tslot(j0 - 3 + p) : 64 * NW * CPT + 6;
-            halo[3 + p] = active ? tslot(j0 + CPT + p) : 64 * NW * CPT + 6;
+        for (int p = 0; p < NG; ++p) {
+            halo[p] = active ? tslot(j0 - NG + p) : 64 * NW * CPT + 2 * NG;
+            halo[NG + p] = active ? tslot(j0 + CPT + p) : 64 * NW * CPT + 2 * NG;
         }
         if (gk >= 0) {
             int64_t cell;
             gpos = 64 * NW * CPT + gk;
-            if (gk < 3) {
-                cell = x0 - 3 + gk;
+            if (gk < NG) {
+                cell = x0 - NG + gk;
             } else {
-                cell = x0 + Tv + (gk - 3);
+                cell = x0 + Tv + (gk - NG);
             }
             cell %= nx;
             if (cell < 0) cell += nx;
@@ -205,73 +220,96 @@ __device__ __forceinline__ void opA_begin(const double (&V)[CPT], double gv, dou
     if (g.gk >= 0) sm.tl[g.gpos] = gv;
     __syncthreads();
 
-    // window w[p] = tile cell j0 - 3 + p, p = 0..CPT+5; past the ragged end it
-    // continues into the right ghost cells (then the scratch slot)
-    double w[CPT + 6];
+    // window w[p] = tile cell j0 - NG + p, p = 0..CPT+2NG-1; past the ragged
+    // end it continues into the right ghost cells (then the scratch slot)
+    constexpr int NG = tile_ghosts<K>();
+    double w[CPT + 2 * NG];
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) w[3 + q] = (RAG && q >= g.nvalid) ? sm.tl[g.tslot(g.j0 + q)] : V[q];
+    for (int q = 0; q < CPT; ++q) w[NG + q] = (RAG && q >= g.nvalid) ? sm.tl[g.tslot(g.j0 + q)] : V[q];
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < NG; ++p) {
         w[p] = sm.tl[g.halo[p]];
-        w[CPT + 3 + p] = sm.tl[g.halo[3 + p]];
+        w[CPT + NG + p] = sm.tl[g.halo[NG + p]];
     }
     double um[CPT], up[CPT];
     double um_l = 0.0, up_r = 0.0;  // u^- in ghost cell -1, u^+ in ghost cell Tv
-    const int pr = 3 + (RAG ? g.nvalid : CPT);  // window position of ghost cell Tv (last thread)
-    static_assert(K <= 2, "split lines keep three ghost cells per side: WENO degree <= 2");
+    const int pr = NG + (RAG ? g.nvalid : CPT);  // window position of ghost cell Tv (last thread)
     if constexpr (K == 0) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
-            um[q] = w[3 + q];
-            up[q] = w[3 + q];
+            um[q] = w[NG + q];
+            up[q] = w[NG + q];
         }
-        um_l = w[2];
+        um_l = w[NG - 1];
         if (g.t == g.tlast) {
 #pragma unroll
-            for (int p = 3; p <= CPT + 3; ++p)
+            for (int p = NG; p <= CPT + NG; ++p)
                 if (p == pr) up_r = w[p];
         }
     } else if constexpr (K == 1) {
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) weno3_cell(w[q + 2], w[q + 3], w[q + 4], pc.eps, um[q], up[q]);
+        for (int q = 0; q < CPT; ++q) weno3_cell(w[q + NG - 1], w[q + NG], w[q + NG + 1], pc.eps, um[q], up[q]);
         if (g.t == 0) {
             double unused;
-            weno3_cell(w[1], w[2], w[3], pc.eps, um_l, unused);
+            weno3_cell(w[NG - 2], w[NG - 1], w[NG], pc.eps, um_l, unused);
         }
         if (g.t == g.tlast) {
-            if (!RAG || pr == CPT + 3) {
+            if (!RAG || pr == CPT + NG) {
                 double unused;
-                weno3_cell(w[CPT + 2], w[CPT + 3], w[CPT + 4], pc.eps, unused, up_r);
+                weno3_cell(w[CPT + NG - 1], w[CPT + NG], w[CPT + NG + 1], pc.eps, unused, up_r);
             } else {
 #pragma unroll
                 for (int q = 0; q < CPT; ++q)
-                    if (q + 3 == pr) up_r = up[q];
+                    if (q + NG == pr) up_r = up[q];
             }
         }
-    } else {
-        double E[CPT + 6];
+    } else if constexpr (K == 2) {
+        double E[CPT + 2 * NG];
 #pragma unroll
-        for (int p = 1; p <= CPT + 4; ++p) E[p] = weno5_e(w[p - 1], w[p], w[p + 1], pc.eps);
+        for (int p = NG - 2; p <= CPT + NG + 1; ++p) E[p] = weno5_e(w[p - 1], w[p], w[p + 1], pc.eps);
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
-            const int p = q + 3;
+            const int p = q + NG;
             weno5_cell(w[p - 2], w[p - 1], w[p], w[p + 1], w[p + 2], E[p - 1], E[p], E[p + 1], um[q], up[q]);
         }
         if (g.t == 0) {
             double unused;
-            weno5_cell(w[0], w[1], w[2], w[3], w[4], E[1], E[2], E[3], um_l, unused);
+            const int p = NG - 1;
+            weno5_cell(w[p - 2], w[p - 1], w[p], w[p + 1], w[p + 2], E[p - 1], E[p], E[p + 1], um_l, unused);
         }
         if (g.t == g.tlast) {
-            if (!RAG || pr == CPT + 3) {
+            if (!RAG || pr == CPT + NG) {
                 double unused;
-                weno5_cell(w[CPT + 1], w[CPT + 2], w[CPT + 3], w[CPT + 4], w[CPT + 5], E[CPT + 2], E[CPT + 3],
-                           E[CPT + 4], unused, up_r);
+                const int p = CPT + NG;
+                weno5_cell(w[p - 2], w[p - 1], w[p], w[p + 1], w[p + 2], E[p - 1], E[p], E[p + 1], unused, up_r);
             } else {
                 // the ragged thread's ghost cell sits inside its window: its u^+
                 // is the mirror reconstruction already computed at that position
 #pragma unroll
                 for (int q = 0; q < CPT; ++q)
-                    if (q + 3 == pr) up_r = up[q];
+                    if (q + NG == pr) up_r = up[q];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int p = q + NG;
+            weno7_cell(w[p - 3], w[p - 2], w[p - 1], w[p], w[p + 1], w[p + 2], w[p + 3], pc.eps, um[q], up[q]);
+        }
+        if (g.t == 0) {
+            double unused;
+            const int p = NG - 1;
+            weno7_cell(w[p - 3], w[p - 2], w[p - 1], w[p], w[p + 1], w[p + 2], w[p + 3], pc.eps, um_l, unused);
+        }
+        if (g.t == g.tlast) {
+            if (!RAG || pr == CPT + NG) {
+                double unused;
+                const int p = CPT + NG;
+                weno7_cell(w[p - 3], w[p - 2], w[p - 1], w[p], w[p + 1], w[p + 2], w[p + 3], pc.eps, unused, up_r);
+            } else {
+#pragma unroll
+                for (int q = 0; q < CPT; ++q)
+                    if (q + NG == pr) up_r = up[q];
             }
         }
     }
@@ -315,7 +353,7 @@ __device__ __forceinline__ void opA_begin(const double (&V)[CPT], double gv, dou
     // two edge interfaces of the tile itself in LDS for the ghost cells
     const int r = (int)(ts.ep % kTileRing);
     double* mine = ts.slot(ts.tile, r);
-    const bool edge_owner = g.active && (g.j0 < 3 || g.j0 + g.nvalid > g.Tv - 3);
+    const bool edge_owner = g.active && (g.j0 < NG || g.j0 + g.nvalid > g.Tv - NG);
     if (threadIdx.x == 0 || edge_owner) __builtin_amdgcn_s_waitcnt(0);
     if (threadIdx.x == 0) {
         // the wave maxima stay in LDS until the next stage's reduction
@@ -329,14 +367,14 @@ __device__ __forceinline__ void opA_begin(const double (&V)[CPT], double gv, dou
         for (int q = 0; q < CPT; ++q) {
             const int cell = g.j0 + q;
             if (RAG && q >= g.nvalid) continue;
-            if (cell < 3) {
+            if (cell < NG) {
                 store_agent(mine + 1 + cell, Fa[q + 1]);
-                store_agent(mine + 4 + cell, Fb[q + 1]);
+                store_agent(mine + 1 + NG + cell, Fb[q + 1]);
             }
-            const int rr = cell - (g.Tv - 3);
+            const int rr = cell - (g.Tv - NG);
             if (rr >= 0) {
-                store_agent(mine + 7 + rr, Fa[q]);
-                store_agent(mine + 10 + rr, Fb[q]);
+                store_agent(mine + 1 + 2 * NG + rr, Fa[q]);
+                store_agent(mine + 1 + 3 * NG + rr, Fb[q]);
             }
         }
     }
@@ -356,11 +394,12 @@ __device__ __forceinline__ void opA_begin(const double (&V)[CPT], double gv, dou
     }
 }
 
-template <int CPT, int NW, bool RAG, bool ROE = false>
+template <int CPT, int NW, int K, bool RAG, bool ROE = false>
 __device__ __forceinline__ bool opA_end(const double (&Fa)[CPT + 1], const double (&Fb)[CPT + 1],
                                         double (&A)[CPT], double& gA, const TGeo<CPT, NW>& g,
                                         const TSmem<CPT, NW>& sm, double* misc, const PhiConst& pc, TSync& ts)
 {
+    constexpr int NG = tile_ghosts<K>();
     // wave 0 polls the G tile maxima and the neighbours' 12 edge values
     const int r = (int)(ts.ep % kTileRing);
     ts.ep += 1;
@@ -369,17 +408,17 @@ __device__ __forceinline__ bool opA_end(const double (&Fa)[CPT + 1], const doubl
         const int G = ts.G;
         double mx = 0.0;
         int bad = 0;
-        for (int it = lane; it < G + 12; it += 64) {
+        for (int it = lane; it < G + 4 * NG; it += 64) {
             const double* src;
             int dst = -1;
             if (it < G) {
                 src = ts.slot(it, r);
             } else {
-                // items G..G+5: the left neighbour's right-edge (Fa, Fb);
-                // G+6..G+11: the right neighbour's left-edge (Fa, Fb)
+                // items G..G+2NG-1: the left neighbour's right-edge (Fa, Fb);
+                // G+2NG..G+4NG-1: the right neighbour's left-edge (Fa, Fb)
                 const int e = it - G;
-                const int nb = (e < 6) ? (ts.tile + G - 1) % G : (ts.tile + 1) % G;
-                src = ts.slot(nb, r) + ((e < 6) ? 7 + e : 1 + (e - 6));
+                const int nb = (e < 2 * NG) ? (ts.tile + G - 1) % G : (ts.tile + 1) % G;
+                src = ts.slot(nb, r) + ((e < 2 * NG) ? 1 + 2 * NG + e : 1 + (e - 2 * NG));
                 dst = 5 + e;
             }
             unsigned long long bits = load_bits(src);
@@ -417,14 +456,14 @@ __device__ __forceinline__ bool opA_end(const double (&Fa)[CPT + 1], const doubl
             for (int q = 0; q < CPT; ++q) {
                 const int cell = g.j0 + q;
                 if (RAG && q >= g.nvalid) continue;
-                if (cell < 3) {
+                if (cell < NG) {
                     store_empty(old + 1 + cell);
-                    store_empty(old + 4 + cell);
+                    store_empty(old + 1 + NG + cell);
                 }
-                const int rr = cell - (g.Tv - 3);
+                const int rr = cell - (g.Tv - NG);
                 if (rr >= 0) {
-                    store_empty(old + 7 + rr);
-                    store_empty(old + 10 + rr);
+                    store_empty(old + 1 + 2 * NG + rr);
+                    store_empty(old + 1 + 3 * NG + rr);
                 }
             }
         }
@@ -443,26 +482,27 @@ __device__ __forceinline__ bool opA_end(const double (&Fa)[CPT + 1], const doubl
         // (Fa, Fb) at the left and right faces of the ghost cell
         double faL, fbL, faR, fbR;
         const int k = g.gk;
-        if (k < 2) {  // cells -3, -2: the left neighbour's faces
+        if (k < NG - 1) {  // cells -NG .. -2: the left neighbour's faces
             faL = misc[5 + k];
-            fbL = misc[8 + k];
+            fbL = misc[5 + NG + k];
             faR = misc[6 + k];
-            fbR = misc[9 + k];
-        } else if (k == 2) {  // cell -1: its right face is the tile's left edge
-            faL = misc[7];
-            fbL = misc[10];
+            fbR = misc[6 + NG + k];
+        } else if (k == NG - 1) {  // cell -1: its right face is the tile's left edge
+            faL = misc[5 + k];
+            fbL = misc[5 + NG + k];
             faR = misc[1];
             fbR = misc[2];
-        } else if (k == 3) {  // cell Tv: its left face is the tile's right edge
+        } else if (k == NG) {  // cell Tv: its left face is the tile's right edge
             faL = misc[3];
             fbL = misc[4];
-            faR = misc[11];
-            fbR = misc[14];
-        } else {  // cells Tv+1, Tv+2: the right neighbour's faces
-            faL = misc[11 + (k - 4)];
-            fbL = misc[14 + (k - 4)];
-            faR = misc[12 + (k - 4)];
-            fbR = misc[15 + (k - 4)];
+            faR = misc[5 + 2 * NG];
+            fbR = misc[5 + 3 * NG];
+        } else {  // cells Tv+1 .. Tv+NG-1: the right neighbour's faces
+            const int r2 = k - NG;
+            faL = misc[5 + 2 * NG + r2 - 1];
+            fbL = misc[5 + 3 * NG + r2 - 1];
+            faR = misc[5 + 2 * NG + r2];
+            fbR = misc[5 + 3 * NG + r2];
         }
         gA = (fma(-alpha, fbL, faL) - fma(-alpha, fbR, faR)) * pc.half_inv_dx;
     }
@@ -476,7 +516,7 @@ __device__ __forceinline__ bool op_A_t(const double (&V)[CPT], double gv, double
 {
     double Fa[CPT + 1], Fb[CPT + 1];
     opA_begin<CPT, NW, K, RAG, ROE>(V, gv, Fa, Fb, g, sm, sm.misc, pc, ts);
-    return opA_end<CPT, NW, RAG, ROE>(Fa, Fb, A, gA, g, sm, sm.misc, pc, ts);
+    return opA_end<CPT, NW, K, RAG, ROE>(Fa, Fb, A, gA, g, sm, sm.misc, pc, ts);
 }
 
 // x <- Phi(x), ghost gx alongside (eq SSPRK1/2/3)
@@ -776,7 +816,7 @@ __device__ __forceinline__ bool lane_step(const SweepArgs& a, int k, int nst, TL
                                           const TSmem<CPT, NW>& sm, double* misc, TSync& ts)
 {
     double A[CPT], gA;
-    if (!opA_end<CPT, NW, RAG, ROE>(L.Fa, L.Fb, A, gA, g, sm, misc, a.pc, ts)) return false;
+    if (!opA_end<CPT, NW, K, RAG, ROE>(L.Fa, L.Fb, A, gA, g, sm, misc, a.pc, ts)) return false;
     const int j = k / ST, st = k - j * ST;
     const double dt = (END == END_RESTRICT && j == chunk_jobs<END>(a) - 1) ? a.dt_next : a.dt;
     if (ST == 1) {
@@ -853,12 +893,12 @@ __device__ __forceinline__ void tiled_body_t(const SweepArgs& a)
     if (a.flag != nullptr && *a.flag != 0) return;
     extern __shared__ double smem_raw[];
     TSmem<CPT, NW> sm;
-    sm.init(smem_raw);
+    sm.template init<tile_ghosts<K>()>(smem_raw);
     const int G = a.tiles;
     const int tile = blockIdx.x % G;
     const int grp = blockIdx.x / G;
     TGeo<CPT, NW> g;
-    g.init(a.nx, tile, G);
+    g.template init<tile_ghosts<K>()>(a.nx, tile, G);
     TSync ts;
     ts.cnt = nullptr;
     ts.ring = kTileRing;
@@ -933,7 +973,7 @@ __device__ __forceinline__ void tiled_batch_body(const BatchLaunch& t)
 {
     extern __shared__ double smem_raw[];
     TSmem<CPT, NW> sm;
-    sm.init(smem_raw);
+    sm.template init<tile_ghosts<K>()>(smem_raw);
     const int G = t.tiles;
     const int tile = blockIdx.x % G;
     const int grp = blockIdx.x / G;
@@ -955,7 +995,7 @@ __device__ __forceinline__ void tiled_batch_body(const BatchLaunch& t)
         const SweepArgs a = t.args[t.problem[lo]];
         if (a.flag != nullptr && *a.flag != 0) continue;
         TGeo<CPT, NW> g;
-        g.init(a.nx, tile, G);
+        g.template init<tile_ghosts<K>()>(a.nx, tile, G);
         if (!tiled_chunk<CPT, NW, K, ST, RAG, END, ROE>(a, j - t.offset[lo], g, sm, ts)) return;
     }
 }

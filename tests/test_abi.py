@@ -238,6 +238,5 @@ def test_split_autotune_validation_without_gpu(lib):
     assert lib.mgrit_autotune_tiled(C.byref(s), 64, 2, None, 0, 1, *args) == mgrit.MGRIT_EINVAL
     assert b"scratch" in lib.mgrit_last_error()
     assert lib.mgrit_autotune_tiled(C.byref(mgrit.euler_scheme(64)), 64, 2, None, 0, 1, *args) == mgrit.MGRIT_EUNSUPPORTED
-    assert lib.mgrit_autotune_tiled(C.byref(mgrit.scheme(8192, k=3)), 64, 2, None, 0, 1, *args) == mgrit.MGRIT_EUNSUPPORTED
     assert lib.mgrit_autotune_tiled(C.byref(s), 0, 2, None, 0, 1, *args) == mgrit.MGRIT_EINVAL
     assert n.value == 0

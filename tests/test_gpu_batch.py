@@ -171,3 +171,26 @@ def test_w3_full_size(orc, gpu):
         assert close_hist(hs[idx], h1), (idx, hs[idx], h1)
     del us
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("levels,relax", [(2, 1), (3, 0)])
+def test_batch_weno7_split_lines(gpu, levels, relax):
+    """WENO7 (four ghost cells per tile side) in batches with split lines of
+    both fluxes: every problem bitwise equal to its own solve."""
+    nxs = [300, 4098, 6002, 8192, 1000]
+    m = 4
+    g = np.random.default_rng(40 + levels)
+    probs = []
+    for i, nx in enumerate(nxs):
+        flux = i % 2
+        a = float(g.uniform(0.5, 1.5)) if flux == 1 else 1.0
+        u0 = W.random_lines(500 + i, 1, nx)[0]
+        speed = np.max(np.abs(u0)) if flux == 0 else a
+        nt = 8 * m
+        probs.append((gpu.scheme(nx, flux=flux, a=a, k=3), nt, 0.5 / nx / speed, u0))
+    p = gpu.params(0, 0.0, m, levels, relax=relax, max_iter=2, tol=-1.0, storage=0, sync_every=2)
+    ub, hb, ib, sb = run_batch(gpu, probs, p)
+    for i, prob in enumerate(probs):
+        us, hs, n, rc = run_single(gpu, prob, p)
+        assert same(ub[i], us), (i, prob[0].nx)
+        assert close_hist(hb[i], hs), (i, hb[i], hs)

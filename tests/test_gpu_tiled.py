@@ -165,6 +165,45 @@ def test_cycle_split_is_bitwise(orc, tiled, relax, cycle):
     assert np.all(rel_lines(ub, uo) < TOL)
 
 
+@pytest.mark.parametrize("cfg", [(1, 4), (2, 8)])
+def test_cycle_weno7_split_is_bitwise(orc, tiled, cfg):
+    """WENO7 (four ghost cells per tile side): two FCF V-cycles on 3 levels,
+    split vs one workgroup per line bitwise, and equal to the oracle."""
+    nx, nt, m, levels = 1000, 64, 4, 3
+    u0 = W.shock_lines(62, 1, nx)[0]
+    dt = 0.8 / m ** (levels - 1) / nx / np.max(np.abs(u0))
+    s = tiled.scheme(nx, k=3)
+    p = tiled.params(nt, dt, m, levels, relax=1, max_iter=2, tol=-1.0)
+
+    def run():
+        ug = T(np.zeros((nt + 1, nx)))
+        tiled.cycle(s, p, T(u0), ug)
+        return H(ug)
+
+    ua = run()
+    tiled.set_tiled_config(nx, nx, *cfg)
+    ub = run()
+    assert np.array_equal(ua, ub)
+    uo, ho, no, sto = orc.mgrit(orc.scheme(nx, k=3), orc.params(nt, dt, m, levels, relax=1, max_iter=2, tol=-1.0),
+                                u0)
+    assert np.all(rel_lines(ub, uo) < TOL)
+
+
+def test_cycle_weno7_long_line_vs_oracle(orc, gpu):
+    """A 6002-cell WENO7 line on its default split: one FCF V-cycle against
+    the oracle."""
+    nx, nt, m, levels = 6002, 32, 4, 2
+    assert gpu.tiled_config(nx)[2] >= 2
+    u0 = W.random_lines(63, 1, nx)[0]
+    dt = 0.8 / m / nx / np.max(np.abs(u0))
+    p = gpu.params(nt, dt, m, levels, relax=1, max_iter=1, tol=-1.0)
+    ug = T(np.zeros((nt + 1, nx)))
+    gpu.cycle(gpu.scheme(nx, k=3), p, T(u0), ug)
+    uo, ho, no, sto = orc.mgrit(orc.scheme(nx, k=3), orc.params(nt, dt, m, levels, relax=1, max_iter=1, tol=-1.0),
+                                u0)
+    assert np.all(rel_lines(H(ug), uo) < TOL)
+
+
 def test_many_line_groups_twice(tiled):
     """512 chunks of 1024 cells on 2 tiles each, so that hundreds of line
     groups are resident at once, launched twice in a row (every group's
@@ -210,7 +249,7 @@ def test_benchmark_cycle_split_is_bitwise(tiled):
 # lines longer than one workgroup holds (default split)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("nx", [4098, 6002, 8192, 65536])
-@pytest.mark.parametrize("k,stepper,flux", [(2, 3, 0), (2, 3, 1), (0, 1, 0)])
+@pytest.mark.parametrize("k,stepper,flux", [(2, 3, 0), (2, 3, 1), (0, 1, 0), (3, 3, 0), (3, 2, 1)])
 def test_phi_long_lines_vs_oracle(orc, gpu, nx, k, stepper, flux):
     cpt, waves, tiles = gpu.tiled_config(nx)
     assert tiles >= 2
