@@ -73,10 +73,12 @@ enum {
  *            central cell's state (sec 2.1.1), take alpha_LF as the largest
  *            |lambda_k| (eq eigs) and, with the Roe flux, Roe averages
  *            (sec 2.1.3; u and H weighted by sqrt(h) or sqrt(rho)) and
- *            alpha_k = l_k . (u+ - u-) with the left eigenvectors.  They run
- *            on lines of at most 512 cells; batches, the adjoint, the
- *            autotuner and fine-integrator matching cover scalar laws only
- *            (MGRIT_EUNSUPPORTED / MGRIT_EINVAL).
+ *            alpha_k = l_k . (u+ - u-) with the left eigenvectors.  Lines
+ *            of up to 512 cells run on one workgroup, longer ones (up to
+ *            65536 cells) on split lines of at most 510 cells per tile, with
+ *            bitwise the same results (mgrit_set_sys_tiles); batches, the
+ *            adjoint, the autotuner and fine-integrator matching cover scalar
+ *            laws only (MGRIT_EUNSUPPORTED / MGRIT_EINVAL).
  *   k        WENO polynomial degree (sec 2.1.1), order s = 2k+1: 0 = piecewise
  *            constant (u^-_{i+1/2} = u_i, u^+_{i+1/2} = u_{i+1}); 1 = WENO3;
  *            2 = WENO5-JS with the printed k = 2 tables; 3 = WENO7.  Stencil
@@ -378,10 +380,24 @@ int mgrit_tiled_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves, in
 
 /* split lines of nx_lo..nx_hi cells into tiles of at most
    64 * waves * cells_per_thread cells (balanced lengths), with a compiled
-   split-line pair: (1,4), (2,4), (2,8), (4,4), (4,8), (4,16).
+   split-line pair: (1,4), (2,4), (2,8), (2,16), (4,4), (4,8), (4,16).
    cells_per_thread == 0 clears every such setting.  Lines must give tiles of
-   at least 3 cells.  Not thread safe. */
+   at least 4 cells.  Scalar laws only (systems: mgrit_set_sys_tiles).  Not
+   thread safe. */
 int mgrit_set_tiled_config(int32_t nx_lo, int32_t nx_hi, int32_t cells_per_thread, int32_t waves);
+
+/* Systems (flux 2, 3) on split lines (sec 2.1.1 per tile): lines of
+   nx_lo..nx_hi cells run on `tiles` workgroups, one cell per thread, the
+   line cut into tiles of balanced length, each of 4..510 cells (else
+   MGRIT_EINVAL); each tile keeps k + 1 ghost cells per side and exchanges
+   alpha_LF and its edge faces' flux parts with the other tiles once per
+   Runge-Kutta stage, so results are bitwise those of one workgroup per line.
+   Lines of more than 512 cells split by default into the fewest tiles of at
+   most 510 cells.  tiles == 0 clears every such setting.  Not thread safe. */
+int mgrit_set_sys_tiles(int32_t nx_lo, int32_t nx_hi, int32_t tiles);
+
+/* tiles per line of system scheme s (1: one workgroup) */
+int mgrit_sys_tiles(const mgrit_scheme* s, int32_t* tiles);
 
 /* the same with the number of time intervals (chunks) each workgroup of a
    split line advances together: 1, or 2 (the two chunks run half a

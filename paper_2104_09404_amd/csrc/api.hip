@@ -84,7 +84,8 @@ bool cfg_compiled(int cpt, int nw)
 const int kLatencyLines = 256;
 
 // systems (flux 2: shallow water, 3: Euler): D components per cell, one cell
-// per thread, lines of at most kMaxSysLine cells
+// per thread; lines of at most kMaxSysLine cells on one workgroup, longer ones
+// split (choose_sys_tiled)
 const int kMaxSysLine = 512;
 int ncomp(const mgrit_scheme* s) { return s->flux == 2 ? 2 : (s->flux == 3 ? 3 : 1); }
 bool is_system(const mgrit_scheme* s) { return s->flux >= 2; }
@@ -227,6 +228,46 @@ int device_tile_scratch(char** out)
     return MGRIT_OK;
 }
 
+// Systems: lines of up to kMaxSysLine cells run on one workgroup, longer ones
+// on tiles of at most kSysTile cells (one cell per thread and two spare
+// threads in a workgroup of at most 512), as few tiles as hold the line, up to
+// kMaxSysTiledLine cells.  mgrit_set_sys_tiles sets the tile count for a
+// range of line lengths (also below kMaxSysLine).
+const int kSysTile = 510;
+const int kMaxSysTiledLine = 1 << 16;
+
+struct SysTileOverride {
+    int nx_lo, nx_hi, tiles;
+};
+std::vector<SysTileOverride> g_sys_tile_overrides;
+
+bool sys_tiles_ok(int n, int G, int k)
+{
+    const int ng = (k == 3) ? 4 : 3;
+    return G >= 1 && (n + G - 1) / G + 2 <= 512 && n / G >= ng;
+}
+
+// tiles and threads per workgroup for a system line of s->nx cells, or false
+// when it runs on one workgroup
+bool choose_sys_tiled(const mgrit_scheme* s, int* tiles, int* threads)
+{
+    const int n = s->nx;
+    int G = 0;
+    for (const SysTileOverride& o : g_sys_tile_overrides)
+        if (n >= o.nx_lo && n <= o.nx_hi) {
+            if (sys_tiles_ok(n, o.tiles, s->k)) G = o.tiles;
+            break;
+        }
+    if (G == 0) {
+        if (n <= kMaxSysLine || n > kMaxSysTiledLine) return false;
+        G = (n + kSysTile - 1) / kSysTile;
+        if (!sys_tiles_ok(n, G, s->k)) return false;
+    }
+    *tiles = G;
+    *threads = 64 * (((n + G - 1) / G + 2 + 63) / 64);
+    return true;
+}
+
 // Adjoint configurations (no register spills): the line must be a multiple of
 // the cells per thread and fit one workgroup.
 const int kMaxAdjLine = 64 * 8 * 2;
@@ -309,8 +350,10 @@ int check_scheme(const mgrit_scheme* s)
             return fail(MGRIT_EINVAL, "shallow water: a is the gravitational constant and must be positive");
         if (s->flux == 3 && !(s->a > 1.0 && std::isfinite(s->a)))
             return fail(MGRIT_EINVAL, "Euler: a is the ratio of specific heats and must exceed 1");
-        if (s->nx > kMaxSysLine)
-            return fail(MGRIT_EUNSUPPORTED, "systems run on lines of at most %d cells, nx = %d", kMaxSysLine, s->nx);
+        int G = 0, threads = 0;
+        if (s->nx > kMaxSysLine && !choose_sys_tiled(s, &G, &threads))
+            return fail(MGRIT_EUNSUPPORTED, "systems run on lines of at most %d cells, nx = %d", kMaxSysTiledLine,
+                        s->nx);
         return MGRIT_OK;
     }
     KernelCfg c;
@@ -448,12 +491,26 @@ int launch(int kc, const SweepArgs& a_in, const mgrit_scheme* s, hipStream_t st,
     int tiles = 0;
     SweepArgs a = a0;
     if (is_system(s)) {
-        const int threads = ((s->nx + 63) / 64) * 64;
+        int threads = ((s->nx + 63) / 64) * 64;
+        const bool split = choose_sys_tiled(s, &tiles, &threads);
+        if (split) {
+            if (a0.coarse_split || a0.gc_sub != nullptr)
+                return fail(MGRIT_EUNSUPPORTED, "a scheme per level does not run on split lines");
+            char* scratch = tl_tile_scratch;
+            if (scratch == nullptr) {
+                int rc = device_tile_scratch(&scratch);
+                if (rc) return rc;
+            }
+            a.tiles = tiles;
+            a.tile_sync = (unsigned long long*)scratch;
+            a.tile_pub = (double*)(scratch + mgk::tile_sync_bytes());
+        }
         ProfLaunch pl;
         int rc = pl.begin(kc, phi_lines, phi_lines * (double)s->nx, st);
         if (rc) return rc;
-        hipError_t e = mgk::launch_sys(a, threads, s->flux, s->k, s->stepper, st);
-        if (e != hipSuccess) return hip_fail(e, "system sweep kernel launch");
+        hipError_t e = split ? mgk::launch_sys_tiled(a, threads, s->flux, s->k, s->stepper, st)
+                             : mgk::launch_sys(a, threads, s->flux, s->k, s->stepper, st);
+        if (e != hipSuccess) return hip_fail(e, split ? "split-line system sweep kernel launch" : "system sweep kernel launch");
         return pl.end(st);
     }
     const bool tiled = choose_tiled(s->nx, &cfg, &tiles);
@@ -604,7 +661,9 @@ Layout make_layout(const mgrit_scheme* s, const mgrit_params* p)
     const int nch0 = (ly.L > 1) ? p->nt / p->m : 1;
     KernelCfg tc;
     int tiles = 0;
-    ly.tiles = (!is_system(s) && choose_tiled(s->nx, &tc, &tiles)) ? tiles : 1;
+    int threads = 0;
+    if (is_system(s)) ly.tiles = choose_sys_tiled(s, &tiles, &threads) ? tiles : 1;
+    else ly.tiles = choose_tiled(s->nx, &tc, &tiles) ? tiles : 1;
     ly.side_off = off;
     off = align256(off + line * (size_t)(nch0 + 1));
     ly.partial_off = off;
@@ -1083,6 +1142,32 @@ int mgrit_set_tiled_config(int32_t nx_lo, int32_t nx_hi, int32_t cpt, int32_t wa
     if (!tiled_compiled(cpt, waves)) return fail(MGRIT_EINVAL, "tiled configuration (%d, %d) is not compiled", cpt, waves);
     if (nx_lo > nx_hi || nx_lo < 8) return fail(MGRIT_EINVAL, "empty range or nx_lo < 8");
     g_tiled_overrides.insert(g_tiled_overrides.begin(), TiledOverride{nx_lo, nx_hi, KernelCfg{cpt, waves}});
+    return MGRIT_OK;
+}
+
+int mgrit_set_sys_tiles(int32_t nx_lo, int32_t nx_hi, int32_t tiles)
+{
+    if (tiles == 0) {
+        g_sys_tile_overrides.clear();
+        return MGRIT_OK;
+    }
+    if (tiles < 1) return fail(MGRIT_EINVAL, "tiles must be >= 1 (0 clears)");
+    if (nx_lo > nx_hi || nx_lo < 8) return fail(MGRIT_EINVAL, "empty range or nx_lo < 8");
+    if ((nx_hi + tiles - 1) / tiles + 2 > 512 || nx_lo / tiles < 4)
+        return fail(MGRIT_EINVAL, "%d tiles do not split lines of %d..%d cells into 4..510 cells each", tiles, nx_lo,
+                    nx_hi);
+    g_sys_tile_overrides.insert(g_sys_tile_overrides.begin(), SysTileOverride{nx_lo, nx_hi, tiles});
+    return MGRIT_OK;
+}
+
+int mgrit_sys_tiles(const mgrit_scheme* s, int32_t* tiles)
+{
+    int rc = check_scheme(s);
+    if (rc) return rc;
+    if (!is_system(s)) return fail(MGRIT_EINVAL, "not a system (flux 2 or 3)");
+    int G = 1, threads = 0;
+    if (!choose_sys_tiled(s, &G, &threads)) G = 1;
+    if (tiles) *tiles = G;
     return MGRIT_OK;
 }
 
@@ -1581,8 +1666,9 @@ int mgrit_cycle_levels(const mgrit_scheme* schemes, const mgrit_params* p, const
     }
     KernelCfg c;
     int tiles = 0;
-    if (mixed && !is_system(s0) && choose_tiled(s0->nx, &c, &tiles))
-        return fail(MGRIT_EUNSUPPORTED, "a scheme per level runs on lines of one workgroup (at most %d cells)", kMaxLine);
+    int threads = 0;
+    if (mixed && (is_system(s0) ? choose_sys_tiled(s0, &tiles, &threads) : choose_tiled(s0->nx, &c, &tiles)))
+        return fail(MGRIT_EUNSUPPORTED, "a scheme per level runs on lines of one workgroup");
     const mgrit_scheme* sl[16];
     for (int l = 0; l < 16; ++l) sl[l] = &schemes[l < p->levels ? l : p->levels - 1];
     return run_cycle(sl, p, u0, u, workspace, ws_bytes, res_hist, iters, stream);

@@ -86,6 +86,26 @@ hipError_t launch_sys(const SweepArgs& a, int threads, int flux, int k, int step
     return hipErrorInvalidValue;
 }
 
+template <int SYS, int K>
+hipError_t launch_sys_tiled_sk(const SweepArgs& a, int threads, int stepper, hipStream_t s);
+
+hipError_t launch_sys_tiled(const SweepArgs& a, int threads, int flux, int k, int stepper, hipStream_t s)
+{
+    if (a.nchunks <= 0) return hipSuccess;
+#define MGK_SYS_K(SYS)                                                        \
+    switch (k) {                                                              \
+    case 0: return launch_sys_tiled_sk<SYS, 0>(a, threads, stepper, s);       \
+    case 1: return launch_sys_tiled_sk<SYS, 1>(a, threads, stepper, s);       \
+    case 2: return launch_sys_tiled_sk<SYS, 2>(a, threads, stepper, s);       \
+    case 3: return launch_sys_tiled_sk<SYS, 3>(a, threads, stepper, s);       \
+    default: return hipErrorInvalidValue;                                     \
+    }
+    if (flux == 2) { MGK_SYS_K(2) }
+    if (flux == 3) { MGK_SYS_K(3) }
+#undef MGK_SYS_K
+    return hipErrorInvalidValue;
+}
+
 // split lines: WENO degree 0 .. 3 (3 or 4 ghost cells per side)
 hipError_t launch_tiled(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
 {

@@ -115,6 +115,8 @@ struct BatchNorm {
 // (one 128-byte line each, so that groups do not contend for a line), and the
 // largest resident grid the synchronisation scratch is sized for
 constexpr int kTileSlot = 24;  // at least 1 + 4 x (ghost cells per side)
+// systems on split lines: at least 1 + 4 x (ghost cells per side) x components
+constexpr int kSysTileSlot = 56;
 constexpr int kTileCounterStride = 16;
 constexpr int kTileMaxWorkgroups = 8192;
 // forward split-line sweeps publish into a ring of 3 slots per tile (the
@@ -274,6 +276,8 @@ hipError_t launch_broadcast(const double* src, double* dst, int64_t nx, int64_t 
 hipError_t launch_fill_wave(double* u, int64_t nx, int64_t nlines, hipStream_t s);
 // systems (flux 2: shallow water, 3: Euler): one workgroup of `threads` per line
 hipError_t launch_sys(const SweepArgs& a, int threads, int flux, int k, int stepper, hipStream_t s);
+// systems on split lines: a.tiles workgroups of `threads` per line (sys_tiled_impl.h)
+hipError_t launch_sys_tiled(const SweepArgs& a, int threads, int flux, int k, int stepper, hipStream_t s);
 hipError_t launch_clear_ints(int* p, int n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long value, int64_t n, hipStream_t s);
 hipError_t launch_sumsq_norm(const double* r, int64_t n, double* out, hipStream_t s);

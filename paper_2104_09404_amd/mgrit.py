@@ -29,7 +29,8 @@ EXPORTED = ["mgrit_phi", "mgrit_serial", "mgrit_relax", "mgrit_residual", "mgrit
             "mgrit_adjoint_workspace_bytes", "mgrit_adjoint", "mgrit_tiled_config", "mgrit_set_tiled_config",
             "mgrit_batched_workspace_bytes", "mgrit_cycle_batched", "mgrit_cycle_levels",
             "mgrit_set_profiling_mask", "mgrit_autotune_scratch_bytes", "mgrit_autotune",
-            "mgrit_cycle_noalloc", "mgrit_set_tiled_intervals", "mgrit_tiled_intervals", "mgrit_autotune_tiled"]
+            "mgrit_cycle_noalloc", "mgrit_set_tiled_intervals", "mgrit_tiled_intervals", "mgrit_autotune_tiled",
+            "mgrit_set_sys_tiles", "mgrit_sys_tiles"]
 
 # size of the library's static workspace of mgrit_cycle_noalloc (MGRIT_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -138,6 +139,8 @@ def load(path: str = LIB_PATH):
     L.mgrit_get_profile.argtypes = [C.POINTER(ProfileEntry), C.c_int]
     L.mgrit_kernel_config.argtypes = [i32, i32, C.POINTER(i32), C.POINTER(i32)]
     L.mgrit_set_kernel_config.argtypes = [i32, i32, i32, i32, i32]
+    L.mgrit_set_sys_tiles.argtypes = [i32, i32, i32]
+    L.mgrit_sys_tiles.argtypes = [S, C.POINTER(i32)]
     L.mgrit_phi_vjp.argtypes = [S, C.c_double, dp, dp, dp, i64, vp]
     L.mgrit_checkpoints.argtypes = [S, C.c_double, i32, i32, dp, dp, vp]
     L.mgrit_adjoint_workspace_bytes.argtypes = [S, i32, i32, i32]
@@ -453,6 +456,22 @@ def tiled_intervals(nx: int) -> int:
 
 def clear_tiled_config():
     _check(load().mgrit_set_tiled_config(0, 0, 0, 0))
+
+
+def set_sys_tiles(nx_lo: int, nx_hi: int, tiles: int):
+    """Run system lines of nx_lo..nx_hi cells on ``tiles`` workgroups each."""
+    _check(load().mgrit_set_sys_tiles(nx_lo, nx_hi, tiles))
+
+
+def clear_sys_tiles():
+    _check(load().mgrit_set_sys_tiles(0, 0, 0))
+
+
+def sys_tiles(s: Scheme) -> int:
+    """Workgroups per line of system scheme s (1: one workgroup)."""
+    t = C.c_int32(0)
+    _check(load().mgrit_sys_tiles(C.byref(s), C.byref(t)))
+    return t.value
 
 
 def phi_vjp(s: Scheme, dt: float, u, lam_in, lam_out, stream=None):

@@ -196,13 +196,33 @@ def test_autotune_validation_without_gpu(lib):
 
 def test_system_validation_without_gpu(lib):
     """Systems: the flux parameter is checked (g > 0, gamma > 1), lines are
-    limited to 512 cells, and the cycle workspace holds D x nx doubles per
+    limited to 65536 cells (split above 512: the fewest tiles of at most 510
+    cells, with the synchronisation scratch in the cycle workspace), tile
+    settings are validated, and the cycle workspace holds D x nx doubles per
     node."""
     from paper_2104_09404_amd import mgrit
 
     assert lib.mgrit_phi(C.byref(mgrit.shallow_water_scheme(64, g=0.0)), 1e-3, None, None, 1, None) == mgrit.MGRIT_EINVAL
     assert lib.mgrit_phi(C.byref(mgrit.euler_scheme(64, gamma=1.0)), 1e-3, None, None, 1, None) == mgrit.MGRIT_EINVAL
-    assert lib.mgrit_phi(C.byref(mgrit.euler_scheme(513)), 1e-3, None, None, 1, None) == mgrit.MGRIT_EUNSUPPORTED
+    assert lib.mgrit_phi(C.byref(mgrit.euler_scheme(65537)), 1e-3, None, None, 1, None) == mgrit.MGRIT_EUNSUPPORTED
+    assert mgrit.sys_tiles(mgrit.euler_scheme(512)) == 1
+    assert mgrit.sys_tiles(mgrit.euler_scheme(513)) == 2
+    assert mgrit.sys_tiles(mgrit.shallow_water_scheme(1020, k=3)) == 2
+    assert mgrit.sys_tiles(mgrit.shallow_water_scheme(1021)) == 3
+    assert mgrit.sys_tiles(mgrit.euler_scheme(65536)) == 129
+    with pytest.raises(mgrit.MgritError):
+        mgrit.sys_tiles(mgrit.scheme(1000))
+    assert lib.mgrit_set_sys_tiles(8, 100, 30) == mgrit.MGRIT_EINVAL  # 0-cell tiles
+    assert lib.mgrit_set_sys_tiles(100, 1100, 2) == mgrit.MGRIT_EINVAL  # 550-cell tiles
+    assert lib.mgrit_set_sys_tiles(12, 100, 3) == mgrit.MGRIT_OK
+    assert mgrit.sys_tiles(mgrit.euler_scheme(64)) == 3
+    assert mgrit.sys_tiles(mgrit.euler_scheme(12, k=3)) == 3  # 4-cell tiles hold WENO7's 4 ghost cells
+    mgrit.clear_sys_tiles()
+    assert mgrit.sys_tiles(mgrit.euler_scheme(64)) == 1
+    pb = mgrit.params(512, 1e-3, 8, 2)
+    one = lib.mgrit_workspace_bytes(C.byref(mgrit.euler_scheme(512)), C.byref(pb))
+    two = lib.mgrit_workspace_bytes(C.byref(mgrit.euler_scheme(513)), C.byref(pb))
+    assert two - one > 10e6  # the split-line synchronisation scratch
     assert lib.mgrit_phi(C.byref(mgrit.scheme(64, flux=4)), 1e-3, None, None, 1, None) == mgrit.MGRIT_EINVAL
     p = mgrit.params(512, 1e-3, 8, 2)
     n1 = lib.mgrit_workspace_bytes(C.byref(mgrit.scheme(64)), C.byref(p))

@@ -186,8 +186,8 @@ def test_systems_unsupported_calls(gpu):
         gpu.phi_vjp(s, 1e-3, w, w, w)
     with pytest.raises(gpu.MgritError):
         gpu.autotune(s, 16, 2)
-    big = gpu.shallow_water_scheme(1024)
-    v = T(np.ones((1, 2 * 1024)))
+    big = gpu.shallow_water_scheme(70000)
+    v = T(np.ones((1, 2 * 70000)))
     with pytest.raises(gpu.MgritError):
         gpu.phi(big, 1e-4, v, v)
     p = gpu.params(0, 0.0, 4, 2, relax=1, max_iter=1, tol=-1.0)
