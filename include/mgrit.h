@@ -147,8 +147,9 @@ typedef struct {
  *             rediscretisation (the scheme with step m^l dt); 1 zeroth-order
  *             (eq coarseLFord0) or 2 first-order (eq coarseLFord1) matching of
  *             M = m^l steps of the fine scheme (eq fineLFxM), for the fine
- *             scheme of eq fineLF only (k = 0, stepper 1, lf_dx_dt = 1) and
- *             lines of at most 4096 cells.
+ *             scheme of eq fineLF only (k = 0, stepper 1, lf_dx_dt = 1); on
+ *             split lines each application of the average or the difference
+ *             exchanges the tiles' edge cells.
  */
 typedef struct {
     int32_t nt;

@@ -623,10 +623,6 @@ int check_params(const mgrit_scheme* s, const mgrit_params* p)
     if (p->coarse_integrator != 0) {
         if (s->k != 0 || s->stepper != 1 || s->lf_dx_dt != 1 || is_system(s))
             return fail(MGRIT_EINVAL, "fine-integrator matching needs the scheme of eq fineLF (k = 0, stepper 1, lf_dx_dt 1)");
-        KernelCfg c;
-        int t = 0;
-        if (choose_tiled(s->nx, &c, &t))
-            return fail(MGRIT_EUNSUPPORTED, "fine-integrator matching runs on lines of at most 4096 cells");
     }
     if (!(p->tol == p->tol)) return fail(MGRIT_EINVAL, "tol is NaN");
     int rc = check_dt(p->dt);

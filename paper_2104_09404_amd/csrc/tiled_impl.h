@@ -181,6 +181,32 @@ __device__ __forceinline__ void store_empty(double* p)
     __hip_atomic_store((unsigned long long*)p, kSlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Empties every slot value this thread may have written at the previous
+// stage (of any kind: thread 0 the maximum, the owners of the NG first and
+// NG last cells their edge values), so that each slot position is always
+// written and emptied by one and the same thread.
+template <int CPT, int NW, int NG, bool RAG>
+__device__ __forceinline__ void empty_own(double* old, const TGeo<CPT, NW>& g)
+{
+    if (threadIdx.x == 0) store_empty(old);
+    if (g.active) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int cell = g.j0 + q;
+            if (RAG && q >= g.nvalid) continue;
+            if (cell < NG) {
+                store_empty(old + 1 + cell);
+                store_empty(old + 1 + NG + cell);
+            }
+            const int rr = cell - (g.Tv - NG);
+            if (rr >= 0) {
+                store_empty(old + 1 + 2 * NG + rr);
+                store_empty(old + 1 + 3 * NG + rr);
+            }
+        }
+    }
+}
+
 // A(V) on the tile (eq spaceDisc, eq LFflux) and on the ghost cell gv of
 // threads 0..5.  RAG: some tile of the line ends inside a thread.  Returns
 // false when the line's synchronisation failed.
@@ -448,26 +474,7 @@ __device__ __forceinline__ bool opA_end(const double (&Fa)[CPT + 1], const doubl
 
     // every tile has now published this stage, so every reader is done with
     // the previous one: its writers empty that slot (used again 3 stages on)
-    {
-        double* old = ts.slot(ts.tile, (r + kTileRing - 1) % kTileRing);
-        if (threadIdx.x == 0) store_empty(old);
-        if (g.active) {
-#pragma unroll
-            for (int q = 0; q < CPT; ++q) {
-                const int cell = g.j0 + q;
-                if (RAG && q >= g.nvalid) continue;
-                if (cell < NG) {
-                    store_empty(old + 1 + cell);
-                    store_empty(old + 1 + NG + cell);
-                }
-                const int rr = cell - (g.Tv - NG);
-                if (rr >= 0) {
-                    store_empty(old + 1 + 2 * NG + rr);
-                    store_empty(old + 1 + 3 * NG + rr);
-                }
-            }
-        }
-    }
+    empty_own<CPT, NW, NG, RAG>(ts.slot(ts.tile, (r + kTileRing - 1) % kTileRing), g);
 
     const double alpha = misc[0];
     const bool ok = misc[39] == 0.0;
@@ -559,6 +566,157 @@ __device__ __forceinline__ bool phi_t(double (&x)[CPT], double& gx, double dt, c
         gx = rk3_third(gx, gv, gA, tdt);
     }
     return true;
+}
+
+// ---------------------------------------------------------------------------
+// fine-integrator matching (sec 3.3.1) on split lines: the average E and the
+// central difference D of psi (sweep_impl.h) need each cell's two
+// neighbours; at the tile's edges those are the neighbour tiles' edge cells,
+// exchanged once per operator application through the same slots.
+// ---------------------------------------------------------------------------
+// One exchange of cell values: the tile publishes its first and last W cells
+// (W = 1: the neighbours of the edge cells for E and D; W = NG: the ghost
+// cells of the neighbours) at the positions their owners use for edge data
+// at a Runge-Kutta stage, plus a zero maximum, and wave 0 reads every tile's
+// maximum (so the ring's rule for emptying holds unchanged) and the
+// neighbours' values: misc[5 + e], e < W the left neighbour's cell Tv - W + e,
+// e >= W the right neighbour's cell e - W.  Every thread that emptied slot
+// values waits for those stores before the barrier, so the tile's maximum,
+// published after it, orders them before any reader's next use of the slot.
+template <int CPT, int NW, int NG, bool RAG, int W>
+__device__ __forceinline__ bool tile_swap(const double (&v)[CPT], const TGeo<CPT, NW>& g, double* misc, TSync& ts)
+{
+    const bool edge_owner = g.active && (g.j0 < NG || g.j0 + g.nvalid > g.Tv - NG);
+    if (threadIdx.x == 0 || edge_owner) __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int r = (int)(ts.ep % kTileRing);
+    ts.ep += 1;
+    double* mine = ts.slot(ts.tile, r);
+    if (threadIdx.x == 0) store_agent(mine, 0.0);
+    if (g.active) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int cell = g.j0 + q;
+            if (RAG && q >= g.nvalid) continue;
+            if (cell < W) store_agent(mine + 1 + cell, v[q]);
+            const int rr = cell - (g.Tv - W);
+            if (rr >= 0) store_agent(mine + 1 + 2 * NG + (NG - W) + rr, v[q]);
+        }
+    }
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int G = ts.G;
+        int bad = 0;
+        for (int it = lane; it < G + 2 * W; it += 64) {
+            const double* src;
+            int dst = -1;
+            if (it < G) {
+                src = ts.slot(it, r);
+            } else {
+                const int e = it - G;
+                src = (e < W) ? ts.slot((ts.tile + G - 1) % G, r) + 1 + 2 * NG + (NG - W) + e
+                              : ts.slot((ts.tile + 1) % G, r) + 1 + (e - W);
+                dst = 5 + e;
+            }
+            unsigned long long bits = load_bits(src);
+            long long spins = 0;
+            while (bits == kSlotEmpty) {
+                if (__hip_atomic_load(ts.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                    ++spins > kTileSpinLimit) {
+                    __hip_atomic_store(ts.err, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bad = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                bits = load_bits(src);
+            }
+            if (dst >= 0) misc[dst] = bad ? 0.0 : __longlong_as_double((long long)bits);
+        }
+        const bool any_bad = __ballot(bad) != 0;
+        if (lane == 0) misc[39] = any_bad ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    empty_own<CPT, NW, NG, RAG>(ts.slot(ts.tile, (r + kTileRing - 1) % kTileRing), g);
+    return misc[39] == 0.0;
+}
+
+// out = E(v) (avg) or D(v) (diff) on the tile, the operations of ed_op; out may alias v
+template <int CPT, int NW, int NG, bool RAG, bool DIFF>
+__device__ __forceinline__ bool ed_t(const double (&v)[CPT], double (&out)[CPT], const TGeo<CPT, NW>& g,
+                                     const TSmem<CPT, NW>& sm, const PhiConst& pc, TSync& ts)
+{
+    __syncthreads();  // earlier readers of the line are done
+    if (g.active) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+            if (!RAG || q < g.nvalid) sm.tl[g.own(q)] = v[q];
+    }
+    if (!tile_swap<CPT, NW, NG, RAG, 1>(v, g, sm.misc, ts)) return false;
+    const int last = RAG ? g.nvalid - 1 : CPT - 1;
+    const double nl = (g.t == 0) ? sm.misc[5] : sm.tl[g.tslot(g.j0 - 1)];
+    const double nr = (g.t == g.tlast) ? sm.misc[6] : sm.tl[g.tslot(g.j0 + last + 1)];
+    double r[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const double left = (q == 0) ? nl : v[q - 1];
+        const double right = (q == last) ? nr : ((q + 1 < CPT) ? v[q + 1] : nr);
+        r[q] = DIFF ? (right - left) * pc.half_inv_dx : 0.5 * (right + left);
+    }
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) out[q] = r[q];
+    return true;
+}
+
+// x <- Psi(x) on the tile (the steps of psi, sweep_impl.h), then the ghost
+// cells take their owners' new values
+template <int CPT, int NW, int NG, bool RAG>
+__device__ __forceinline__ bool psi_t(double (&x)[CPT], double& gx, int order, int M, double dt,
+                                      const TGeo<CPT, NW>& g, const TSmem<CPT, NW>& sm, const PhiConst& pc, TSync& ts)
+{
+    double f[CPT], T[CPT], v[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        v[q] = x[q];
+        f[q] = flux_f(x[q], pc.fa, pc.fb);
+    }
+    if (!ed_t<CPT, NW, NG, RAG, true>(f, T, g, sm, pc, ts)) return false;
+    if (order == 0) {
+        for (int r = 0; r < M; ++r)
+            if (!ed_t<CPT, NW, NG, RAG, false>(v, v, g, sm, pc, ts)) return false;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) x[q] = v[q] - (double)M * dt * T[q];
+    } else {
+        for (int k = 1; k < M; ++k) {
+            if (!ed_t<CPT, NW, NG, RAG, false>(v, v, g, sm, pc, ts)) return false;
+            if (!ed_t<CPT, NW, NG, RAG, false>(T, T, g, sm, pc, ts)) return false;
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) f[q] = flux_f(v[q], pc.fa, pc.fb);
+            double Df[CPT];
+            if (!ed_t<CPT, NW, NG, RAG, true>(f, Df, g, sm, pc, ts)) return false;
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) T[q] = T[q] + Df[q];
+        }
+        if (!ed_t<CPT, NW, NG, RAG, false>(v, v, g, sm, pc, ts)) return false;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) x[q] = v[q] - dt * T[q];
+    }
+    if (!tile_swap<CPT, NW, NG, RAG, NG>(x, g, sm.misc, ts)) return false;
+    if (g.gk >= 0) gx = sm.misc[5 + g.gk];
+    return true;
+}
+
+// one step of the level: Phi, or the matching coarse integrator of M fine
+// steps (forward Euler with the LF flux only, as level_step)
+template <int CPT, int NW, int K, int ST, bool RAG, bool ROE>
+__device__ __forceinline__ bool level_step_t(double (&x)[CPT], double& gx, double dt, int M, const SweepArgs& a,
+                                             const TGeo<CPT, NW>& g, const TSmem<CPT, NW>& sm, const PhiConst& pc,
+                                             TSync& ts)
+{
+    if constexpr (K == 0 && ST == 1 && !ROE) {
+        if (a.psi_order != 0 && M > 0)
+            return psi_t<CPT, NW, tile_ghosts<K>(), RAG>(x, gx, a.psi_order - 1, M, a.dt_fine, g, sm, pc, ts);
+    }
+    return phi_t<CPT, NW, K, ST, RAG, ROE>(x, gx, dt, g, sm, pc, ts);
 }
 
 // line access restricted to the tile's own cells (and the thread's ghost cell)
@@ -661,7 +819,7 @@ __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGe
 
     const int64_t n0 = (int64_t)c * a.m;
     for (int j = 1; j <= a.nsteps; ++j) {
-        if (!phi_t<CPT, NW, K, ST, RAG, ROE>(x, gx, a.dt, g, sm, a.pc, ts)) return false;
+        if (!level_step_t<CPT, NW, K, ST, RAG, ROE>(x, gx, a.dt, a.psi_M, a, g, sm, a.pc, ts)) return false;
         if (a.g != nullptr) t_add<CPT, NW, RAG>(x, gx, a.g + (n0 + j) * nx, g);
         if (a.fout != nullptr) {
             if (a.fout_every <= 1) t_store(x, a.fout + (n0 + j) * nx, g);
@@ -671,12 +829,12 @@ __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGe
 
     if constexpr (END == END_NONE) return true;
     if constexpr (END == END_PHI) {
-        if (!phi_t<CPT, NW, K, ST, RAG, ROE>(x, gx, a.dt, g, sm, a.pc, ts)) return false;
+        if (!level_step_t<CPT, NW, K, ST, RAG, ROE>(x, gx, a.dt, a.psi_M, a, g, sm, a.pc, ts)) return false;
         t_store(x, a.side_out + (int64_t)c * nx, g);
         return true;
     }
     const int64_t n1 = n0 + a.m;
-    if (!phi_t<CPT, NW, K, ST, RAG, ROE>(x, gx, a.dt, g, sm, a.pc, ts)) return false;
+    if (!level_step_t<CPT, NW, K, ST, RAG, ROE>(x, gx, a.dt, a.psi_M, a, g, sm, a.pc, ts)) return false;
     if (a.g != nullptr) t_add<CPT, NW, RAG>(x, gx, a.g + n1 * nx, g);
     const double* cnext = a.cref + (int64_t)(c + 1) * a.cref_stride * nx;
     if (a.resid_partial != nullptr) {
@@ -696,7 +854,10 @@ __device__ __forceinline__ bool tiled_chunk(const SweepArgs& a, int c, const TGe
     else t_store(x, a.uc_out + (int64_t)(c + 1) * nx, g);
     double y[CPT], gy;
     t_load(y, gy, cstart, g);
-    if (!phi_t<CPT, NW, K, ST, RAG, ROE>(y, gy, a.dt_next, g, sm, a.pc, ts)) return false;
+    // the coarse step: its own LF coefficient where the scheme ties it to the step (lf_dx_dt)
+    PhiConst pcn = a.pc;
+    if (a.alpha_next > 0.0) pcn.alpha_fixed = a.alpha_next;
+    if (!level_step_t<CPT, NW, K, ST, RAG, ROE>(y, gy, a.dt_next, a.psi_M_next, a, g, sm, pcn, ts)) return false;
 #pragma unroll
     for (int q = 0; q < CPT; ++q) y[q] = x[q] - y[q];
     t_store(y, a.gc_out + (int64_t)(c + 1) * nx, g);
@@ -816,9 +977,12 @@ __device__ __forceinline__ bool lane_step(const SweepArgs& a, int k, int nst, TL
                                           const TSmem<CPT, NW>& sm, double* misc, TSync& ts)
 {
     double A[CPT], gA;
-    if (!opA_end<CPT, NW, K, RAG, ROE>(L.Fa, L.Fb, A, gA, g, sm, misc, a.pc, ts)) return false;
     const int j = k / ST, st = k - j * ST;
-    const double dt = (END == END_RESTRICT && j == chunk_jobs<END>(a) - 1) ? a.dt_next : a.dt;
+    const bool coarse = END == END_RESTRICT && j == chunk_jobs<END>(a) - 1;
+    PhiConst pcj = a.pc;
+    if (coarse && a.alpha_next > 0.0) pcj.alpha_fixed = a.alpha_next;
+    if (!opA_end<CPT, NW, K, RAG, ROE>(L.Fa, L.Fb, A, gA, g, sm, misc, pcj, ts)) return false;
+    const double dt = coarse ? a.dt_next : a.dt;
     if (ST == 1) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) L.x[q] = rk_first(L.x[q], A[q], dt);
@@ -908,6 +1072,13 @@ __device__ __forceinline__ void tiled_body_t(const SweepArgs& a)
     ts.tile = tile;
     ts.ep = 0;
     if constexpr (PAIR) {
+        if constexpr (K == 0 && ST == 1 && !ROE) {
+            if (a.psi_order != 0) {  // matching integrator: one chunk at a time
+                for (int c = grp; c < a.nchunks; c += a.groups)
+                    if (!tiled_chunk<CPT, NW, K, ST, RAG, END, ROE>(a, c, g, sm, ts)) return;
+                return;
+            }
+        }
         // chunks grp, grp + groups, ... taken two at a time, each with its own slots
         TSync ts2 = ts;
         ts2.pub = ts.pub + (int64_t)G * kTileRing * kTileSlot;

@@ -136,3 +136,103 @@ def test_matching_in_batches(gpu):
         rc, h1, n1 = gpu.cycle(sch, q, T(u0), u1)
         assert np.array_equal(H(us[i]), H(u1))
         np.testing.assert_allclose(hs[i], h1, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# split lines: each application of E and D exchanges the tiles' edge cells
+# ---------------------------------------------------------------------------
+@pytest.fixture
+def tiled(gpu):
+    yield gpu
+    gpu.clear_tiled_config()
+
+
+@pytest.mark.parametrize("ci", [1, 2])
+@pytest.mark.parametrize("relax,cycle", [(0, 0), (1, 1)])
+def test_matching_split_is_bitwise(tiled, ci, relax, cycle):
+    """The largest grid of the fine-matching experiment (2^10 cells, 2^13
+    steps, 5 levels: M up to 16 fine steps matched), 1024 cells on 4 tiles of
+    256 against one workgroup per line: two cycles, iterates bitwise equal."""
+    nx, nt = 1024, 8192
+    u0 = initial("moving", nx)
+    dt = TEND / nt
+    s = tiled.fine_lf_scheme(nx)
+    p = tiled.params(nt, dt, 2, 5, relax=relax, cycle=cycle, max_iter=2, tol=-1.0, coarse_integrator=ci)
+
+    def run():
+        ug = T(np.zeros((nt + 1, nx)))
+        rc, h, n = tiled.cycle(s, p, T(u0), ug)
+        return H(ug), np.array(h)
+
+    ua, ha = run()
+    tiled.set_tiled_config(nx, nx, 1, 4)
+    assert tiled.tiled_config(nx)[2] == 4
+    ub, hb = run()
+    if ci == 2:  # first-order matching converges here (sec 4)
+        assert np.all(np.isfinite(ua))
+    with np.errstate(invalid="ignore"):
+        assert np.all((ua == ub) | (np.isnan(ua) & np.isnan(ub)))
+    np.testing.assert_allclose(hb, ha, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("ci", [1, 2])
+def test_matching_long_line_vs_oracle(orc, gpu, ci):
+    """A 4100-cell line (split by default), 4 levels, two V-cycles with
+    F-relaxation, against the oracle; CFL 0.1 on the fine level, so that both
+    matching orders stay stable up to M = 8 (an unstable coarse integrator
+    amplifies the round-off difference of the two evaluation orders line by
+    line)."""
+    nx, nt, tend = 4100, 2048, 0.05
+    assert gpu.tiled_config(nx)[2] >= 2
+    u0 = initial("moving", nx)
+    dt = tend / nt
+    po = orc.params(nt, dt, 2, 4, relax=0, max_iter=2, tol=-1.0, coarse_integrator=ci)
+    uo, ho, no, sto = orc.mgrit(orc.fine_lf_scheme(nx), po, u0)
+    pg = gpu.params(nt, dt, 2, 4, relax=0, max_iter=2, tol=-1.0, coarse_integrator=ci)
+    ug = T(np.zeros((nt + 1, nx)))
+    gpu.cycle(gpu.fine_lf_scheme(nx), pg, T(u0), ug)
+    assert np.all(rel_lines(H(ug), uo) < TOL)
+
+
+@pytest.mark.parametrize("coarse_guess", [0, 1])
+def test_lf_dx_dt_restriction_split_is_bitwise(tiled, coarse_guess):
+    """The FAS restriction's coarse step of the scheme of eq fineLF takes its
+    own coefficient dx/dt_{l+1} (eq coarseLF) on split lines too."""
+    nx, m, n = 1024, 4, 64
+    u = np.stack([initial("moving", nx)] * (n + 1)) + 1e-3 * np.random.default_rng(3).standard_normal((n + 1, nx))
+    g = 1e-4 * np.random.default_rng(4).standard_normal((n + 1, nx))
+    s = tiled.fine_lf_scheme(nx)
+    dt = 0.2 / nx
+    nc = n // m
+
+    def run():
+        r, uc, gc = T(np.zeros((nc, nx))), T(np.zeros((nc + 1, nx))), T(np.zeros((nc + 1, nx)))
+        tiled.residual(s, dt, m, T(u), T(g), n, coarse_guess=coarse_guess, r=r, u_coarse=uc, g_coarse=gc)
+        return [H(x) for x in (r, uc, gc)]
+
+    a = run()
+    tiled.set_tiled_config(nx, nx, 2, 4)
+    b = run()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_lf_dx_dt_restriction_paired_vs_oracle(orc, tiled):
+    """The same with two chunks per workgroup on a 4100-cell line: equal to
+    one chunk per workgroup bitwise and to the oracle's rediscretised cycle."""
+    nx, nt, tend = 4100, 64, 0.05
+    u0 = initial("stationary", nx)
+    dt = tend / 512
+    p = tiled.params(nt, dt, 4, 2, relax=1, max_iter=1, tol=-1.0)
+
+    def run():
+        ug = T(np.zeros((nt + 1, nx)))
+        tiled.cycle(tiled.fine_lf_scheme(nx), p, T(u0), ug)
+        return H(ug)
+
+    one = run()
+    tiled.set_tiled_intervals(nx, nx, 4, 8, 2)
+    two = run()
+    assert np.array_equal(one, two)
+    uo, _, _, _ = orc.mgrit(orc.fine_lf_scheme(nx), orc.params(nt, dt, 4, 2, relax=1, max_iter=1, tol=-1.0), u0)
+    assert np.all(rel_lines(one, uo) < TOL)
