@@ -4,8 +4,8 @@
 // A line of nx cells is split into G tiles of T = 64*NW*CPT cells (the last
 // tile may be shorter, always a multiple of CPT).  Tile g is owned by one
 // workgroup, which keeps its cells in registers and, per Runge-Kutta stage:
-//   1. mirrors its cells and six ghost cells (three on each side, owned by the
-//      neighbouring tiles) into LDS, barrier;
+//   1. mirrors its cells and 2 NG ghost cells (NG on each side, owned by the
+//      neighbouring tiles; NG = 3, or 4 for WENO7) into LDS, barrier;
 //   2. reconstructs u^-/u^+ of its cells (sec 2.1.1) plus one extra
 //      reconstruction in each edge ghost cell, so that it can form every
 //      interface flux of its cells itself;
@@ -13,13 +13,13 @@
 //      before and after the global coefficient is known,
 //          2F = Fa - alpha_LF Fb,  Fa = f(u^-) + f(u^+),  Fb = u^+ - u^-
 //      (with the Roe flux, eq roeflux, Fa is twice the flux and Fb = 0),
-//      and publishes its local max |u^{+-}| and (Fa, Fb) of the three
+//      and publishes its local max |u^{+-}| and (Fa, Fb) of the NG
 //      interfaces inside each edge to a global slot, straight from the
 //      threads that hold them;
 //   4. polls the slots of the other tiles of the line (each value is its own
 //      arrival flag; bounded spin) for alpha_LF = max over all tiles (eq eigs)
 //      and its neighbours' edge data;
-//   5. updates its cells and, with the neighbours' data, its six ghost cells,
+//   5. updates its cells and, with the neighbours' data, its ghost cells,
 //      evaluating exactly the operations the owners evaluate on the same
 //      operands, so ghosts stay bitwise equal to the owners' cells.
 // One global synchronisation per stage; everything else stays on chip.
@@ -208,13 +208,13 @@ __device__ __forceinline__ void empty_own(double* old, const TGeo<CPT, NW>& g)
 }
 
 // A(V) on the tile (eq spaceDisc, eq LFflux) and on the ghost cell gv of
-// threads 0..5.  RAG: some tile of the line ends inside a thread.  Returns
-// false when the line's synchronisation failed.
+// threads 0..2NG-1.  RAG: some tile of the line ends inside a thread.
+// Returns false when the line's synchronisation failed.
 //
 // Published slot (one per tile and stage, in a ring of kTileRing):
-//   [0] max |u^{+-}| over the tile, [1..3] Fa at the right faces of tile cells
-//   0, 1, 2, [4..6] Fb there, [7..9] Fa at the left faces of cells Tv-3,
-//   Tv-2, Tv-1, [10..12] Fb there.
+//   [0] max |u^{+-}| over the tile, [1..NG] Fa at the right faces of tile
+//   cells 0..NG-1, [NG+1..2NG] Fb there, [2NG+1..3NG] Fa at the left faces of
+//   cells Tv-NG..Tv-1, [3NG+1..4NG] Fb there.
 // Every value is its own arrival flag: a slot holds kSlotEmpty until written,
 // and a reader polls each value it needs until it is no longer empty (64-bit
 // stores and loads are single-copy atomic).  Each value is written by the
@@ -426,7 +426,7 @@ __device__ __forceinline__ bool opA_end(const double (&Fa)[CPT + 1], const doubl
                                         const TSmem<CPT, NW>& sm, double* misc, const PhiConst& pc, TSync& ts)
 {
     constexpr int NG = tile_ghosts<K>();
-    // wave 0 polls the G tile maxima and the neighbours' 12 edge values
+    // wave 0 polls the G tile maxima and the neighbours' 4 NG edge values
     const int r = (int)(ts.ep % kTileRing);
     ts.ep += 1;
     if (threadIdx.x < 64) {
