@@ -17,6 +17,11 @@
         the same shape of F-sweep (512 chunks x 7 SSPRK3 steps) for shallow
         water and Euler on 512-cell lines, WENO degrees 0, 2 and 3, LF and Roe,
         in the order of SYSTEMS.
+    python -m paper_2104_09404_amd.profiling batch [cycles]
+        the 512-problem batch (workloads.w3_batched, 2-level FCF, m = 8,
+        C-point storage): one warm-up call of one cycle, then one
+        mgrit_cycle_batched call of `cycles` cycles (default 2) plus the final
+        residual sweep, timed on the host around a synchronised call.
 """
 from __future__ import annotations
 
@@ -148,6 +153,34 @@ def systems(reps: int = 5, quiet: bool = False) -> dict:
     return out
 
 
+def batch(cycles: int = 2):
+    import time
+
+    import torch
+
+    from . import mgrit
+    from . import workloads as W
+
+    pbs = W.w3_batched()
+    table = []
+    for pb in pbs:
+        u = torch.zeros((pb.nt // pb.m + 1, pb.nx), dtype=torch.float64, device="cuda")
+        table.append((mgrit.scheme_from_problem(pb), pb.nt, pb.dt, torch.from_numpy(pb.u0).cuda(), u))
+    arr = mgrit.problem_table(table)
+
+    def params(it):
+        return mgrit.params(0, 0.0, 8, 2, relax=1, max_iter=it, tol=-1.0, storage=1, sync_every=it)
+
+    ws = torch.empty(mgrit.batched_workspace_bytes(arr, params(cycles)) // 8 + 64, dtype=torch.float64,
+                     device="cuda")
+    mgrit.cycle_batched(arr, params(1), workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mgrit.cycle_batched(arr, params(cycles), workspace=ws)
+    torch.cuda.synchronize()
+    print("batch of %d problems, %d cycles: %.3f s" % (len(pbs), cycles, time.perf_counter() - t0), flush=True)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "copy"
     if what == "copy":
@@ -158,5 +191,7 @@ if __name__ == "__main__":
         variants(int(sys.argv[2]) if len(sys.argv) > 2 else 5)
     elif what == "systems":
         systems(int(sys.argv[2]) if len(sys.argv) > 2 else 5)
+    elif what == "batch":
+        batch(int(sys.argv[2]) if len(sys.argv) > 2 else 2)
     else:
-        raise SystemExit("usage: python -m paper_2104_09404_amd.profiling copy|sweep|variants|systems [n]")
+        raise SystemExit("usage: python -m paper_2104_09404_amd.profiling copy|sweep|variants|systems|batch [n]")
