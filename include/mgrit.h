@@ -10,9 +10,11 @@
  * Conventions shared by every entry point
  *   - All array pointers are DEVICE pointers to contiguous FP64 data owned by
  *     the caller (e.g. torch tensors).  The library never allocates or frees
- *     caller memory.  It allocates device memory only once per device: the
- *     10.5 MB synchronisation buffer of split lines (below), on the first
- *     split-line launch outside mgrit_cycle, kept until the process ends.
+ *     caller memory, and allocates no device memory of its own: split lines
+ *     outside a workspace-taking call synchronise through a static 10.5 MB
+ *     device array (one per device, held while the library is loaded;
+ *     concurrent split-line calls on one device share it, so they must not
+ *     overlap).
  *   - Line length.  Lines of up to 4096 cells run on one workgroup each.
  *     Longer lines (or any range chosen with mgrit_set_tiled_config) are split
  *     into tiles of balanced length, one workgroup per tile, which exchange
@@ -456,8 +458,8 @@ int mgrit_autotune(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, void* 
  *   scratch  device, at least mgrit_autotune_scratch_bytes(s->nx, nlines)
  *            bytes, caller-owned; overwritten with smooth test lines.
  *   cells_per_thread, waves, intervals, ms_best  HOST outputs (may be NULL).
- * Synchronises the stream; uses (and on first use allocates) the device's
- * split-line synchronisation buffer.  Systems return MGRIT_EUNSUPPORTED.
+ * Synchronises the stream; uses the device's static split-line
+ * synchronisation array.  Systems return MGRIT_EUNSUPPORTED.
  * Not thread safe when installing.
  */
 int mgrit_autotune_tiled(const mgrit_scheme* s, int32_t nlines, int32_t nsteps, void* scratch, size_t scratch_bytes,

@@ -17,6 +17,10 @@
 using mgk::KernelCfg;
 using mgk::SweepArgs;
 
+// synchronisation scratch of split-line launches outside a workspace-taking
+// call (device_tile_scratch); host code uses only its hipGetSymbolAddress
+static __device__ __align__(256) char split_scratch[mgk::kTileScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
@@ -207,8 +211,9 @@ bool choose_tiled(int nx, KernelCfg* out, int* tiles)
 
 // Synchronisation scratch of tiled launches: mgrit_cycle takes it from its
 // workspace (set for the duration of the call on the calling thread); the
-// other entry points use one buffer per device, allocated on the first tiled
-// launch on that device and kept until the process ends.
+// other entry points use the static device array split_scratch (one per
+// device, in the library's code object: nothing is allocated), whose address
+// hipGetSymbolAddress gives once per device.
 thread_local char* tl_tile_scratch = nullptr;
 std::mutex g_tile_mutex;
 std::vector<char*> g_tile_scratch;
@@ -221,7 +226,9 @@ int device_tile_scratch(char** out)
     if ((int)g_tile_scratch.size() <= dev) g_tile_scratch.resize(dev + 1, nullptr);
     if (g_tile_scratch[dev] == nullptr) {
         void* p = nullptr;
-        HIP_TRY(hipMalloc(&p, mgk::tile_scratch_bytes()), "hipMalloc of the tiled-line scratch");
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(split_scratch)), "hipGetSymbolAddress of the split-line scratch");
+        if (p == nullptr || ((uintptr_t)p & 255) != 0)
+            return fail(MGRIT_EHIP, "split-line scratch has no 256-byte aligned device address");
         g_tile_scratch[dev] = (char*)p;
     }
     *out = g_tile_scratch[dev];

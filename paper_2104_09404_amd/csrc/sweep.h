@@ -125,15 +125,11 @@ constexpr int kTileRing = 3;
 // bit pattern of an empty slot value: a negative signalling NaN, which no
 // arithmetic result can be (results are quiet NaNs at most)
 constexpr unsigned long long kSlotEmpty = 0xFFF7DEADBEEF0001ull;
-inline size_t tile_sync_bytes()
-{
-    return sizeof(unsigned long long) * kTileCounterStride * (size_t)(kTileMaxWorkgroups + 1);
-}
-inline size_t tile_scratch_bytes()
-{
-    // two chunks per workgroup at most
-    return tile_sync_bytes() + sizeof(double) * (size_t)kTileMaxWorkgroups * 2 * kTileRing * kTileSlot;
-}
+constexpr size_t kTileSyncBytes = sizeof(unsigned long long) * kTileCounterStride * (size_t)(kTileMaxWorkgroups + 1);
+// two chunks per workgroup at most
+constexpr size_t kTileScratchBytes = kTileSyncBytes + sizeof(double) * (size_t)kTileMaxWorkgroups * 2 * kTileRing * kTileSlot;
+inline size_t tile_sync_bytes() { return kTileSyncBytes; }
+inline size_t tile_scratch_bytes() { return kTileScratchBytes; }
 
 // Adjoint launches (adjoint_impl.h): one workgroup per line b.
 struct AdjArgs {
