@@ -17,6 +17,15 @@
         the same shape of F-sweep (512 chunks x 7 SSPRK3 steps) for shallow
         water and Euler on 512-cell lines, WENO degrees 0, 2 and 3, LF and Roe,
         in the order of SYSTEMS.
+    python -m paper_2104_09404_amd.profiling cycle1024 [cycles]
+        only `cycles` V-cycles (default 3) of the N_x = 1024 workload
+        (N_T = 4096, m = 8, 3-level FCF, fixed count), for counter runs on its
+        level-0 sweep kernel without the rest of the benchmark.
+    python -m paper_2104_09404_amd.profiling shortlines [reps]
+        F-sweeps of 4096 chunks of 15 WENO5 + SSPRK3 steps on 256-cell lines
+        (mgrit_relax on 65537 nodes, m = 16) under every compiled
+        one-workgroup shape that covers 256 cells (SHORT_SHAPES), with
+        HIP-event times per sweep.
     python -m paper_2104_09404_amd.profiling batch [cycles]
         the 512-problem batch (workloads.w3_batched, 2-level FCF, m = 8,
         C-point storage): one warm-up call of one cycle, then one
@@ -153,6 +162,57 @@ def systems(reps: int = 5, quiet: bool = False) -> dict:
     return out
 
 
+def cycle1024(cycles: int = 3):
+    import torch
+
+    from . import mgrit
+    from . import workloads as W
+
+    pb = W.w1_burgers_weno5()
+    s = mgrit.scheme_from_problem(pb)
+    p = mgrit.params(pb.nt, pb.dt, pb.m, pb.levels, relax=1, max_iter=cycles, tol=-1.0, sync_every=cycles)
+    u = torch.zeros((pb.nt + 1, pb.nx), dtype=torch.float64, device="cuda")
+    mgrit.cycle(s, p, torch.from_numpy(pb.u0).cuda(), u)
+    torch.cuda.synchronize()
+    print("ran %d cycles of the %d-cell problem" % (cycles, pb.nx))
+
+
+SHORT_SHAPES = [(4, 1), (2, 2), (1, 4), (2, 4), (1, 8)]
+
+
+def shortlines(reps: int = 5, quiet: bool = False) -> dict:
+    import numpy as np
+    import torch
+
+    from . import mgrit
+    from . import workloads as W
+
+    nx, m, n = 256, 16, 65536
+    s = mgrit.scheme(nx)
+    u = torch.from_numpy(W.random_lines(7, 1, nx)).cuda().repeat(n + 1, 1)
+    dt = 0.5 / nx / float(u.abs().max())
+    out = {}
+    for cpt, nw in SHORT_SHAPES:
+        mgrit.clear_kernel_config()
+        mgrit.set_kernel_config(nx, nx, cpt, nw, latency=False)
+        mgrit.relax(s, dt, m, 0, u, None, n)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            mgrit.relax(s, dt, m, 0, u, None, n)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        med = float(np.median(ts))
+        cells = (n // m) * (m - 1) * nx
+        out["%dx%d" % (cpt, nw)] = {"ms": med, "cell_steps_per_s": cells / (med * 1e-3)}
+        if not quiet:
+            print("(%d, %d): %.4f ms per sweep, %.3e cell-steps/s" % (cpt, nw, med, cells / (med * 1e-3)), flush=True)
+    mgrit.clear_kernel_config()
+    return out
+
+
 def batch(cycles: int = 2):
     import time
 
@@ -191,7 +251,12 @@ if __name__ == "__main__":
         variants(int(sys.argv[2]) if len(sys.argv) > 2 else 5)
     elif what == "systems":
         systems(int(sys.argv[2]) if len(sys.argv) > 2 else 5)
+    elif what == "cycle1024":
+        cycle1024(int(sys.argv[2]) if len(sys.argv) > 2 else 3)
+    elif what == "shortlines":
+        shortlines(int(sys.argv[2]) if len(sys.argv) > 2 else 5)
     elif what == "batch":
         batch(int(sys.argv[2]) if len(sys.argv) > 2 else 2)
     else:
-        raise SystemExit("usage: python -m paper_2104_09404_amd.profiling copy|sweep|variants|systems|batch [n]")
+        raise SystemExit("usage: python -m paper_2104_09404_amd.profiling "
+                         "copy|sweep|variants|systems|cycle1024|shortlines|batch [n]")
