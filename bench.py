@@ -42,6 +42,12 @@ METRIC = "WENO5-SSPRK3 fine cell-steps/s in MGRIT relax; adjoint/forward time ra
 # divisions count as one flop
 FLOPS_PER_CELL_STEP = 440.0
 PEAK_FP64 = 78.6e12
+PEAK_HBM = 8.0e12
+# first order (k = 0) LF + forward Euler: two flux evaluations, the LF flux
+# and the difference, the update; one line read and one written per step when
+# every node is stored
+K0_FE_FLOPS_PER_CELL_STEP = 10.0
+K0_FE_BYTES_PER_CELL_STEP = 8.0
 ONE_WG_FC = "relax_fc_kernel<4, 4, 2, 3, false, false>"
 
 
@@ -312,8 +318,20 @@ def run_cycles(mgrit, pb, steps, warmup, dominant="relax_fc_l0", storage=0):
     }
 
 
+def measured_executed_flops(kernel):
+    """Executed FP64 flops per cell-step of ``kernel`` from the
+    SQ_INSTS_VALU_*_F64 counter record profiles/executed_flops.json (FMA = 2,
+    x 64 lanes), or None when missing or the sources changed since."""
+    rec = _record("executed_flops.json")
+    if rec is None or kernel not in rec or not _fresh(rec[kernel]):
+        return None
+    return rec[kernel]["flops_per_cell_step"]
+
+
 def roofline(kernel, desc, r):
     achieved = FLOPS_PER_CELL_STEP * r["dominant_cell_steps_per_launch"] / (r["dominant_avg_launch_ms"] * 1e-3)
+    executed = measured_executed_flops(kernel)
+    rate = r["dominant_cell_steps_per_launch"] / (r["dominant_avg_launch_ms"] * 1e-3)
     return {
         "bound": "alu",
         "kernel": kernel + ": " + desc,
@@ -326,6 +344,10 @@ def roofline(kernel, desc, r):
         "flops_per_cell_step": FLOPS_PER_CELL_STEP,
         "cell_steps_per_launch": r["dominant_cell_steps_per_launch"],
         "avg_launch_ms": r["dominant_avg_launch_ms"],
+        # the counter view: FP64 flops the kernel actually executes (fewer
+        # than the algorithmic count: smoothness indicators serve both faces)
+        "executed_flops_per_cell_step": executed,
+        "executed_frac": None if executed is None else executed * rate / PEAK_FP64,
     }
 
 
@@ -524,6 +546,21 @@ def main():
             "kernel_ms_per_step": r1["kernel_ms_per_step"],
             "mgrit_converges": r1["mgrit_converges"],
             "gpu_serial_ms": gpu_serial_ms(mgrit, s1, w1, torch.from_numpy(w1.u0).cuda()),
+        }
+        w0 = W.w0_burgers_k0()
+        r0 = run_cycles(mgrit, w0, 50, 3, dominant="relax_fr_l0")
+        rate0 = r0["level0_relax_cell_steps_per_s"]
+        out["burgers_k0_fe_nx64"] = {
+            "workload": "Burgers, first-order LF + forward Euler, N_x=64, N_T=256, m=4, 2-level F-relaxation V-cycle, "
+                        "50 fixed cycles (a correctness configuration)",
+            "value": r0["value"], "unit": "cell-steps/s", "ms_per_step": r0["ms_per_step"],
+            "level0_relax_cell_steps_per_s": rate0,
+            "frac_fp64_peak": K0_FE_FLOPS_PER_CELL_STEP * rate0 / PEAK_FP64,
+            "frac_hbm_peak": K0_FE_BYTES_PER_CELL_STEP * rate0 / PEAK_HBM,
+            "note": "64 chunks of 64-cell lines fill 64 wavefronts of a 256-CU GPU: the sweeps are latency bound "
+                    "and neither the FP64 roofline (%g flops per cell-step) nor the HBM roofline (%g B per "
+                    "materialised cell-step) is reachable" % (K0_FE_FLOPS_PER_CELL_STEP, K0_FE_BYTES_PER_CELL_STEP),
+            "kernel_ms_per_step": r0["kernel_ms_per_step"],
         }
         out["batched_512"] = batched(mgrit)
         out["adjoint_forward_ratio"] = None if args.no_adjoint else adjoint_ratio(mgrit)
