@@ -1695,6 +1695,7 @@ struct BatchBucket {
     int nblocks;             // workgroups (one line each), or work items of split lines
     size_t dev_off;          // offset / problem arrays in the workspace
     int tiles;               // split lines: workgroups per line (0: one workgroup per line)
+    int wide;                // lines of one workgroup with several cell blocks per thread (cfg.intervals)
 };
 
 struct BatchPhase {
@@ -1750,6 +1751,25 @@ int check_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p
 // lay out the workspace.  With ws == nullptr only the sizes are computed.
 // tiles of the serial solves of split-line problems in a batch
 const int kBatchSerialTiles = 4;
+
+// Lines of 4097..8192 cells that are a multiple of 4, with the LF flux and
+// Phi steps (no matching integrator), run the many-chunk phases of a batch on
+// one workgroup per line (wide_impl.h): no per-stage exchange between
+// workgroups.  Serial solves stay split (latency), and so do other lines.
+const KernelCfg kBatchWideCfg{4, 8, 4};
+const int kBatchWideMax = 8192;
+
+const KernelCfg kBatchWideCfg2{2, 8, 8};  // even lines that 4 does not divide
+
+bool batch_wide(const mgrit_scheme& s, const SweepArgs& a, bool serial, KernelCfg* c)
+{
+    if (serial || s.nx <= kMaxLine || s.nx > kBatchWideMax || s.numflux != 0 || s.k > 2 || a.psi_order != 0)
+        return false;
+    if (s.nx % kBatchWideCfg.cpt == 0) *c = kBatchWideCfg;
+    else if (s.nx % kBatchWideCfg2.cpt == 0) *c = kBatchWideCfg2;
+    else return false;
+    return true;
+}
 
 int plan_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p, char* ws, BatchPlan* bp)
 {
@@ -1832,8 +1852,13 @@ int plan_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p,
                 KernelCfg c;
                 int t = 0;
                 const bool serial = r.a.nchunks == 1 && r.a.end_mode == mgk::END_NONE;
-                int tiles = 0;
-                if (choose_tiled(probs[i].scheme.nx, &c, &t)) {
+                int tiles = 0, wide = 0;
+                if (batch_wide(probs[i].scheme, r.a, serial, &c)) {
+                    wide = c.intervals;
+                    // the chunk's residual partial sits in the first of the
+                    // layout's per-tile slots, the others are zero
+                    bp->host_args[(base + ph) * count + i].tiles = bp->ly[i].tiles;
+                } else if (choose_tiled(probs[i].scheme.nx, &c, &t)) {
                     if (serial && mgk::tiles_fit(probs[i].scheme.nx, kBatchSerialTiles, 2, 16)) {
                         // serial solves (no residual partials, so any tiling) share one
                         // shape: every split-line problem's solve runs at once, each on
@@ -1863,10 +1888,11 @@ int plan_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p,
                 const int roe = probs[i].scheme.numflux;
                 BatchBucket* bk = nullptr;
                 for (BatchBucket& b : P.buckets)
-                    if (b.cfg.cpt == c.cpt && b.cfg.nw == c.nw && b.ragged == rag && b.roe == roe && b.tiles == tiles)
+                    if (b.cfg.cpt == c.cpt && b.cfg.nw == c.nw && b.ragged == rag && b.roe == roe && b.tiles == tiles &&
+                        b.wide == wide)
                         bk = &b;
                 if (bk == nullptr) {
-                    P.buckets.push_back(BatchBucket{c, rag, roe, {}, {}, 0, 0, tiles});
+                    P.buckets.push_back(BatchBucket{c, rag, roe, {}, {}, 0, 0, tiles, wide});
                     bk = &P.buckets.back();
                 }
                 bk->offset.push_back(bk->nblocks);
@@ -2004,8 +2030,11 @@ int mgrit_cycle_batched(const mgrit_problem* probs, int32_t count, const mgrit_p
                 int prc = pl.begin(P.kc, phi_lines, cells, st);
                 if (prc) return prc;
                 hipError_t e = (b.tiles > 0) ? mgk::launch_tiled_batch(t, b.cfg, k0, st0, st)
-                                             : mgk::launch_batch(t, b.cfg, k0, st0, st);
-                if (e != hipSuccess) return hip_fail(e, b.tiles > 0 ? "batched split-line launch" : "batched sweep kernel launch");
+                               : (b.wide > 0) ? mgk::launch_wide_batch(t, b.cfg, k0, st0, st)
+                                              : mgk::launch_batch(t, b.cfg, k0, st0, st);
+                if (e != hipSuccess)
+                    return hip_fail(e, b.tiles > 0 ? "batched split-line launch"
+                                       : b.wide > 0 ? "batched wide-line launch" : "batched sweep kernel launch");
                 if ((prc = pl.end(st))) return prc;
             }
             for (int i : P.split) {

@@ -210,6 +210,9 @@ hipError_t launch_batch_ks(const BatchLaunch& t, const KernelCfg& cfg, hipStream
 template <int K, int ST>
 hipError_t launch_tiled_batch_ks(const BatchLaunch& t, const KernelCfg& cfg, hipStream_t s);
 
+template <int K, int ST>
+hipError_t launch_wide_batch_ks(const BatchLaunch& t, const KernelCfg& cfg, hipStream_t s);
+
 bool tiled_batch_compiled(const KernelCfg& cfg)
 {
 #define MGK_CASE(C, W) \
@@ -228,6 +231,18 @@ hipError_t launch_tiled_batch(const BatchLaunch& t, const KernelCfg& cfg, int k,
     case 1: MGK_DISPATCH_KS(launch_tiled_batch_ks, 1, t, cfg, s);
     case 2: MGK_DISPATCH_KS(launch_tiled_batch_ks, 2, t, cfg, s);
     case 3: MGK_DISPATCH_KS(launch_tiled_batch_ks, 3, t, cfg, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_wide_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s)
+{
+    if (t.nblocks <= 0) return hipSuccess;
+    switch (k) {
+    case 0: MGK_DISPATCH_KS(launch_wide_batch_ks, 0, t, cfg, s);
+    case 1: MGK_DISPATCH_KS(launch_wide_batch_ks, 1, t, cfg, s);
+    case 2: MGK_DISPATCH_KS(launch_wide_batch_ks, 2, t, cfg, s);
+    case 3: MGK_DISPATCH_KS(launch_wide_batch_ks, 3, t, cfg, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -219,6 +219,14 @@ struct KernelCfg {
     X(2, 16)                        \
     X(4, 8)
 
+// one-workgroup shapes of batches for lines of 4097..8192 cells (wide_impl.h):
+// (cells per thread, waves, virtual threads per thread), the line a multiple
+// of the cells per thread
+#define MGK_WIDE_CFG_LIST(X) \
+    X(4, 16, 2)              \
+    X(4, 8, 4)               \
+    X(2, 8, 8)
+
 #define MGK_TILED_CFG_LIST(X) \
     X(1, 4)                   \
     X(2, 4)                   \
@@ -263,6 +271,8 @@ hipError_t launch_sweep(const SweepArgs& a, const KernelCfg& cfg, int k, int ste
 hipError_t launch_tiled(const SweepArgs& a, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
 hipError_t launch_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
 hipError_t launch_tiled_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
+// one workgroup per line of up to cfg.intervals x 64 cfg.nw x cfg.cpt cells (wide_impl.h)
+hipError_t launch_wide_batch(const BatchLaunch& t, const KernelCfg& cfg, int k, int stepper, hipStream_t s);
 bool tiled_batch_compiled(const KernelCfg& cfg);
 hipError_t launch_reduce_norm_batch(const BatchNorm* tab, int count, double tol, int* converged, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, const KernelCfg& cfg, int k, int stepper, int store_mode, hipStream_t s);

@@ -194,3 +194,24 @@ def test_batch_weno7_split_lines(gpu, levels, relax):
         us, hs, n, rc = run_single(gpu, prob, p)
         assert same(ub[i], us), (i, prob[0].nx)
         assert close_hist(hb[i], hs), (i, hb[i], hs)
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("levels,relax,cycle", [(2, 1, 0), (3, 1, 0), (3, 0, 1)])
+def test_batch_wide_lines(gpu, storage, levels, relax, cycle):
+    """Lines of 4097..8192 cells that are multiples of 4 run the batch's
+    many-chunk phases on one workgroup per line (several cell blocks per
+    thread), their own solves on split lines: every iterate bitwise equal,
+    residual histories to round-off (partials grouped per line instead of
+    per tile); mixed with split and one-workgroup lines, both fluxes."""
+    nxs = [5000, 8192, 4100, 6002, 1000, 7996]
+    m = 4
+    probs = mixed_problems(gpu, nxs, 0.6, m, 30 + levels + storage)
+    p = gpu.params(0, 0.0, m, levels, relax=relax, cycle=cycle, max_iter=3, tol=-1.0, storage=storage,
+                   sync_every=3)
+    ub, hb, ib, sb = run_batch(gpu, probs, p)
+    for i, prob in enumerate(probs):
+        us, hs, n, rc = run_single(gpu, prob, p)
+        assert same(ub[i], us), (i, prob[0].nx)
+        assert ib[i] == n == 3
+        assert close_hist(hb[i], hs), (i, hb[i], hs)
