@@ -183,14 +183,19 @@ int tiles_for(int nx, const KernelCfg& c)
 }
 
 // Configuration and number of tiles for lines of nx cells, or false when a
-// line of nx cells runs in one workgroup.  Default: tiles of whole threads,
-// 4 cells per thread (up to 4096 cells) when 4 divides nx, else 2 cells per
-// thread (up to 2048 cells, 16 waves) when nx is even; odd lines take
-// 2048-cell tiles of 4 cells per thread and 8 waves, whose ragged variant
-// the compiler holds free of register spills.
+// line of nx cells runs in one workgroup.  Default: tiles of whole threads;
+// lines of at least kWideTileLine cells that 16 divides take 8192-cell tiles
+// of 16 cells per thread and 8 waves (2 waves per SIMD, 254 VGPRs): twice the
+// work per tile between two exchanges, measured 13.4 against 16.3 ms for the
+// level-0 sweep of the 65536-cell problem.  Otherwise 4 cells per thread (up
+// to 4096 cells) when 4 divides nx, else 2 cells per thread (up to 2048
+// cells, 16 waves) when nx is even; odd lines take 2048-cell tiles of 4 cells
+// per thread and 8 waves, whose ragged variant the compiler holds free of
+// register spills.
 // Longest split line: 256 tiles of 4096 cells (one per compute unit), or 512
 // tiles of 2048 cells.
 const int kMaxTiledLine = 1 << 20;
+const int kWideTileLine = 32768;
 
 bool choose_tiled(int nx, KernelCfg* out, int* tiles)
 {
@@ -202,7 +207,8 @@ bool choose_tiled(int nx, KernelCfg* out, int* tiles)
             return mgk::tiles_fit(nx, *tiles, o.cfg.cpt, o.cfg.nw);
         }
     if (nx <= kMaxLine) return false;
-    if (nx % 4 == 0) *out = KernelCfg{4, 16};
+    if (nx % 16 == 0 && nx >= kWideTileLine) *out = KernelCfg{16, 8};
+    else if (nx % 4 == 0) *out = KernelCfg{4, 16};
     else if (nx % 2 == 0 && nx <= kMaxTiledLine / 2) *out = KernelCfg{2, 16};
     else *out = KernelCfg{4, 8};
     *tiles = tiles_for(nx, *out);

@@ -234,7 +234,8 @@ struct KernelCfg {
     X(2, 16)                  \
     X(4, 4)                   \
     X(4, 8)                   \
-    X(4, 16)
+    X(4, 16)                  \
+    X(16, 8)
 
 // (cells per thread, waves) pairs compiled for the adjoint of split lines;
 // every tile must be a whole number of threads

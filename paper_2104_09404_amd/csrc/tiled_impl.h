@@ -1101,7 +1101,7 @@ __device__ __forceinline__ void tiled_body_t(const SweepArgs& a)
 // schedule built for that occupancy ran the 65536-cell F-sweep 12 % faster
 // (15.0 against 16.9 ms); ragged tiles keep the compiler's budget, which
 // holds them free of register spills.
-#define MGK_TILED_WAVES_PER_EU (RAG ? 1 : (PAIR && NW < 16) ? 2 : 4)
+#define MGK_TILED_WAVES_PER_EU (RAG ? 1 : ((PAIR && NW < 16) || CPT >= 16) ? 2 : 4)
 template <int CPT, int NW, int K, int ST, bool RAG, bool ROE, bool PAIR>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MGK_TILED_WAVES_PER_EU))) void tiled_relax_f_kernel(
     SweepArgs a)

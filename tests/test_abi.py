@@ -124,18 +124,23 @@ def test_kernel_config_choice(lib):
 
 def test_split_line_choice(lib):
     """Lines up to 4096 cells run on one workgroup; longer ones are split into
-    tiles balanced in whole threads: up to 4096 cells of 4 per thread when 4
-    divides the line, else up to 2048 cells of 2 per thread when it is even,
-    else ragged tiles of up to 2048 cells of 4 per thread."""
+    tiles balanced in whole threads: lines of at least 32768 cells that 16
+    divides into tiles of up to 8192 cells of 16 per thread, else up to 4096
+    cells of 4 per thread when 4 divides the line, else up to 2048 cells of 2
+    per thread when it is even, else ragged tiles of up to 2048 cells of 4 per
+    thread."""
     from paper_2104_09404_amd import mgrit
 
     assert mgrit.tiled_config(4096) == (0, 0, 1)
-    assert mgrit.tiled_config(65536) == (4, 16, 16)
+    assert mgrit.tiled_config(65536) == (16, 8, 8)
+    assert mgrit.tiled_config(32768) == (16, 8, 4)
+    assert mgrit.tiled_config(32772) == (4, 16, 9)
+    assert mgrit.tiled_config(16384) == (4, 16, 4)
     assert mgrit.tiled_config(8192) == (4, 16, 2)
     assert mgrit.tiled_config(6002) == (2, 16, 3)
     assert mgrit.tiled_config(6001) == (4, 8, 3)
     assert mgrit.tiled_config(8190) == (2, 16, 4)
-    assert mgrit.tiled_config(1 << 20) == (4, 16, 256)
+    assert mgrit.tiled_config(1 << 20) == (16, 8, 128)
     assert mgrit.tiled_intervals(65536) == 1
     assert mgrit.tiled_config((1 << 20) + 2) == (0, 0, 1)
     mgrit.set_tiled_config(300, 1000, 1, 4)

@@ -11,7 +11,7 @@ from paper_2104_09404_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
-TILED = [(1, 4), (2, 4), (2, 8), (4, 4), (4, 8)]
+TILED = [(1, 4), (2, 4), (2, 8), (4, 4), (4, 8), (16, 8)]
 
 
 @pytest.fixture(scope="module")
@@ -202,6 +202,31 @@ def test_cycle_weno7_long_line_vs_oracle(orc, gpu):
     uo, ho, no, sto = orc.mgrit(orc.scheme(nx, k=3), orc.params(nt, dt, m, levels, relax=1, max_iter=1, tol=-1.0),
                                 u0)
     assert np.all(rel_lines(H(ug), uo) < TOL)
+
+
+@pytest.mark.parametrize("k,numflux", [(2, 0), (2, 1), (3, 0), (0, 0)])
+def test_wide_tiles_bitwise(tiled, k, numflux):
+    """A 32768-cell line on its default 4 tiles of 8192 cells (16 per thread)
+    against 8 tiles of 4096 (4 per thread): Phi and relaxation bitwise equal."""
+    nx, m, n = 32768, 4, 16
+    assert tiled.tiled_config(nx) == (16, 8, 4)
+    u = W.random_lines(80 + k, n + 1, nx)
+    s = tiled.scheme(nx, k=k, numflux=numflux)
+    dt = 0.6 / nx / np.max(np.abs(u))
+
+    def run():
+        a = T(u)
+        tiled.relax(s, dt, m, 2, a, None, n)
+        out = T(np.zeros((2, nx)))
+        tiled.phi(s, dt, T(u[:2]), out)
+        return H(a), H(out)
+
+    ra = run()
+    tiled.set_tiled_config(nx, nx, 4, 16)
+    assert tiled.tiled_config(nx) == (4, 16, 8)
+    rb = run()
+    for x, y in zip(ra, rb):
+        assert np.array_equal(x, y)
 
 
 def test_many_line_groups_twice(tiled):
