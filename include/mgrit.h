@@ -376,14 +376,28 @@ void mgrit_set_profiling_mask(uint32_t classes);
    Returns MGRIT_EUNSUPPORTED if no compiled configuration covers the line. */
 int mgrit_kernel_config(int32_t nx, int32_t nlines, int32_t* cells_per_thread, int32_t* waves);
 
-/* split-line configuration for lines of nx cells: cells per thread, waves
-   per tile and number of tiles; *tiles == 1 (and zeros) when the line runs on
-   one workgroup. */
+/* split-line configuration for lines of nx cells in launches of many chunks:
+   cells per thread, waves per tile and number of tiles; *tiles == 1 (and
+   zeros) when the line runs on one workgroup. */
 int mgrit_tiled_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves, int32_t* tiles);
+
+/* split-line configuration of one launch over `nchunks` chunks (time
+   intervals, or lines for mgrit_phi; 1 for mgrit_serial and the coarsest
+   solve) of lines of nx cells; `residual` != 0 for a launch that also forms
+   the C-point residual (level-0 relaxation with a residual).  Launches whose
+   mgrit_tiled_config shape would occupy fewer than 256 workgroups (chunks x
+   tiles), write no residual and have no mgrit_set_tiled_config setting for
+   nx take tiles of 1024 cells (2 cells per thread, 8 waves) when nx is even
+   and at most 131072: a stage of such a launch is bound by latency, and
+   smaller tiles shorten it.  Results are bitwise the same for every shape.
+   Outputs as mgrit_tiled_config; MGRIT_EINVAL if nchunks < 0.  Allocates
+   nothing and launches nothing. */
+int mgrit_tiled_launch_config(int32_t nx, int64_t nchunks, int32_t residual, int32_t* cells_per_thread,
+                              int32_t* waves, int32_t* tiles);
 
 /* split lines of nx_lo..nx_hi cells into tiles of at most
    64 * waves * cells_per_thread cells (balanced lengths), with a compiled
-   split-line pair: (1,4), (2,4), (2,8), (2,16), (4,4), (4,8), (4,16).
+   split-line pair: (1,4), (2,4), (2,8), (2,16), (4,4), (4,8), (4,16), (16,8).
    cells_per_thread == 0 clears every such setting.  Lines must give tiles of
    at least 4 cells.  Scalar laws only (systems: mgrit_set_sys_tiles).  Not
    thread safe. */

@@ -215,6 +215,32 @@ bool choose_tiled(int nx, KernelCfg* out, int* tiles)
     return true;
 }
 
+// Split-line launches of few chunks (serial stepping, the coarsest solve,
+// the coarse levels of a cycle) are bound by the latency of one RK stage, not
+// by throughput.  Measured on one line (WENO5 + LF + SSPRK3, per stage):
+// 65536 cells take 8.07 us on 8 tiles of (16, 8), 4.98 on 16 tiles of
+// (4, 16) and 3.85 on 64 tiles of 1024 cells (2 cells per thread, 8 waves);
+// from 8192 to 131072 cells the 1024-cell tiles stay within 12 % of the
+// fastest compiled shape.  An even line of at most kLatencyTiledLine cells
+// takes them when the default shape would occupy fewer than kLatencyLines
+// workgroups (chunks x tiles) and no override covers its length.  Launches
+// that write residual partials keep the default shape: its tile count sizes
+// the partial buffer.  Results are bitwise those of every other shape.
+const int kLatencyTiledLine = 131072;
+
+void latency_tiled(int nx, int64_t nchunks, bool resid, KernelCfg* cfg, int* tiles)
+{
+    if (resid || nx % 2 != 0 || nx > kLatencyTiledLine) return;
+    for (const TiledOverride& o : g_tiled_overrides)
+        if (nx >= o.nx_lo && nx <= o.nx_hi) return;
+    if (nchunks * (int64_t)*tiles >= kLatencyLines) return;
+    const KernelCfg c{2, 8};
+    const int G = tiles_for(nx, c);
+    if (!mgk::tiles_fit(nx, G, c.cpt, c.nw)) return;
+    *cfg = c;
+    *tiles = G;
+}
+
 // Synchronisation scratch of tiled launches: mgrit_cycle takes it from its
 // workspace (set for the duration of the call on the calling thread); the
 // other entry points use the static device array split_scratch (one per
@@ -527,6 +553,7 @@ int launch(int kc, const SweepArgs& a_in, const mgrit_scheme* s, hipStream_t st,
         return pl.end(st);
     }
     const bool tiled = choose_tiled(s->nx, &cfg, &tiles);
+    if (tiled) latency_tiled(s->nx, a.nchunks, a.resid_partial != nullptr, &cfg, &tiles);
     if (tiled && (a0.coarse_split || a0.gc_sub != nullptr))
         return fail(MGRIT_EUNSUPPORTED, "a scheme per level does not run on split lines");
     if (tiled) {
@@ -1114,6 +1141,24 @@ int mgrit_tiled_config(int32_t nx, int32_t* cells_per_thread, int32_t* waves, in
     KernelCfg c{0, 0};
     int G = 1;
     if (!choose_tiled(nx, &c, &G)) {
+        c = KernelCfg{0, 0};
+        G = 1;
+    }
+    if (cells_per_thread) *cells_per_thread = c.cpt;
+    if (waves) *waves = c.nw;
+    if (tiles) *tiles = G;
+    return MGRIT_OK;
+}
+
+int mgrit_tiled_launch_config(int32_t nx, int64_t nchunks, int32_t residual, int32_t* cells_per_thread,
+                              int32_t* waves, int32_t* tiles)
+{
+    if (nchunks < 0) return fail(MGRIT_EINVAL, "nchunks must be >= 0");
+    KernelCfg c{0, 0};
+    int G = 1;
+    if (choose_tiled(nx, &c, &G)) {
+        latency_tiled(nx, nchunks, residual != 0, &c, &G);
+    } else {
         c = KernelCfg{0, 0};
         G = 1;
     }

@@ -30,7 +30,7 @@ EXPORTED = ["mgrit_phi", "mgrit_serial", "mgrit_relax", "mgrit_residual", "mgrit
             "mgrit_batched_workspace_bytes", "mgrit_cycle_batched", "mgrit_cycle_levels",
             "mgrit_set_profiling_mask", "mgrit_autotune_scratch_bytes", "mgrit_autotune",
             "mgrit_cycle_noalloc", "mgrit_set_tiled_intervals", "mgrit_tiled_intervals", "mgrit_autotune_tiled",
-            "mgrit_set_sys_tiles", "mgrit_sys_tiles"]
+            "mgrit_set_sys_tiles", "mgrit_sys_tiles", "mgrit_tiled_launch_config"]
 
 # size of the library's static workspace of mgrit_cycle_noalloc (MGRIT_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -139,6 +139,7 @@ def load(path: str = LIB_PATH):
     L.mgrit_get_profile.argtypes = [C.POINTER(ProfileEntry), C.c_int]
     L.mgrit_kernel_config.argtypes = [i32, i32, C.POINTER(i32), C.POINTER(i32)]
     L.mgrit_set_kernel_config.argtypes = [i32, i32, i32, i32, i32]
+    L.mgrit_tiled_launch_config.argtypes = [i32, i64, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     L.mgrit_set_sys_tiles.argtypes = [i32, i32, i32]
     L.mgrit_sys_tiles.argtypes = [S, C.POINTER(i32)]
     L.mgrit_phi_vjp.argtypes = [S, C.c_double, dp, dp, dp, i64, vp]
@@ -434,6 +435,16 @@ def tiled_config(nx: int):
     when a line runs on one workgroup."""
     c, w, t = C.c_int32(0), C.c_int32(0), C.c_int32(0)
     _check(load().mgrit_tiled_config(nx, C.byref(c), C.byref(w), C.byref(t)))
+    return c.value, w.value, t.value
+
+
+def tiled_launch_config(nx: int, nchunks: int, residual: bool = False):
+    """(cells per thread, waves, tiles) of one split-line launch over nchunks
+    chunks of lines of nx cells: launches of few chunks that form no residual
+    take 1024-cell tiles (latency bound), others the tiled_config shape."""
+    c, w, t = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    _check(load().mgrit_tiled_launch_config(nx, nchunks, 1 if residual else 0, C.byref(c), C.byref(w),
+                                            C.byref(t)))
     return c.value, w.value, t.value
 
 

@@ -159,6 +159,38 @@ def test_split_line_choice(lib):
     assert n_split > 2 * n_one
 
 
+def test_split_line_latency_choice(lib):
+    """One launch over few chunks that forms no residual (serial stepping, the
+    coarsest solve, coarse levels) takes 1024-cell tiles of 2 cells per thread
+    and 8 waves when the many-chunk shape would occupy fewer than 256
+    workgroups, the line is even and at most 131072 cells, and no
+    set_tiled_config setting covers it; every other launch keeps the
+    many-chunk shape."""
+    from paper_2104_09404_amd import mgrit
+
+    mgrit.clear_tiled_config()
+    assert mgrit.tiled_launch_config(65536, 1) == (2, 8, 64)
+    assert mgrit.tiled_launch_config(65536, 31) == (2, 8, 64)  # 31 x 8 = 248 workgroups
+    assert mgrit.tiled_launch_config(65536, 32) == (16, 8, 8)  # 256
+    assert mgrit.tiled_launch_config(65536, 1, residual=True) == (16, 8, 8)
+    assert mgrit.tiled_launch_config(8192, 127) == (2, 8, 8)
+    assert mgrit.tiled_launch_config(8192, 128) == (4, 16, 2)
+    assert mgrit.tiled_launch_config(6002, 1) == (2, 8, 6)
+    assert mgrit.tiled_launch_config(6001, 1) == (4, 8, 3)  # odd: the ragged default
+    assert mgrit.tiled_launch_config(131072, 1) == (2, 8, 128)
+    assert mgrit.tiled_launch_config(131074, 1) == (2, 16, 65)  # longer: the default
+    assert mgrit.tiled_launch_config(1 << 20, 1) == (16, 8, 128)
+    assert mgrit.tiled_launch_config(4096, 1) == (0, 0, 1)  # one workgroup per line
+    assert mgrit.tiled_launch_config(65536, 0) == (2, 8, 64)
+    with pytest.raises(mgrit.MgritError):
+        mgrit.tiled_launch_config(65536, -1)
+    mgrit.set_tiled_config(65536, 65536, 4, 16)
+    try:
+        assert mgrit.tiled_launch_config(65536, 1) == (4, 16, 16)
+    finally:
+        mgrit.clear_tiled_config()
+
+
 def test_batch_validation_without_gpu(lib):
     """Batches: the workspace is sized on the host; mixed k or stepper, fewer
     than two levels or an empty batch are rejected before any device call."""

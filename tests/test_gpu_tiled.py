@@ -229,6 +229,39 @@ def test_wide_tiles_bitwise(tiled, k, numflux):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("k", [2, 3])
+def test_latency_tiles_bitwise(tiled, k):
+    """Launches of few chunks that form no residual take 1024-cell tiles
+    (16 per 16384-cell line instead of 4): serial stepping, Phi, relaxation
+    and a two-level cycle (whose residual sweeps keep the default tiles)
+    bitwise equal to every launch on the default tiles."""
+    nx, m, n, nt = 16384, 4, 16, 64
+    assert tiled.tiled_launch_config(nx, 1) == (2, 8, 16)
+    assert tiled.tiled_launch_config(nx, 16, residual=True) == (4, 16, 4)
+    u = W.random_lines(90 + k, n + 1, nx)
+    s = tiled.scheme(nx, k=k)
+    dt = 0.6 / nx / np.max(np.abs(u))
+    p = tiled.params(nt, dt, m, 2, relax=1, max_iter=3, tol=-1.0)
+
+    def run():
+        traj = T(np.zeros((nt + 1, nx)))
+        tiled.serial(s, dt, nt, T(u[0]), traj)
+        a = T(u)
+        tiled.relax(s, dt, m, 2, a, None, n)
+        out = T(np.zeros((2, nx)))
+        tiled.phi(s, dt, T(u[:2]), out)
+        ug = T(np.zeros((nt + 1, nx)))
+        _, hist, _ = tiled.cycle(s, p, T(u[0]), ug)
+        return H(traj), H(a), H(out), H(ug), np.array(hist)
+
+    ra = run()
+    tiled.set_tiled_config(nx, nx, 4, 16)
+    assert tiled.tiled_launch_config(nx, 1) == (4, 16, 4)
+    rb = run()
+    for x, y in zip(ra, rb):
+        assert np.array_equal(x, y, equal_nan=True)
+
+
 def test_many_line_groups_twice(tiled):
     """512 chunks of 1024 cells on 2 tiles each, so that hundreds of line
     groups are resident at once, launched twice in a row (every group's
