@@ -238,10 +238,14 @@ __device__ __forceinline__ void opA_begin(const double (&V)[CPT], double gv, dou
                                           const TSmem<CPT, NW>& sm, double* misc, const PhiConst& pc,
                                           const TSync& ts)
 {
+    // the LDS mirror: the windows of other threads read only the first and
+    // last NG cells of a whole thread (every cell when CPT <= 2 NG); ragged
+    // tiles, where a window may reach past a short thread, mirror every cell
+    constexpr int NGW = tile_ghosts<K>();
     if (g.active) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q)
-            if (!RAG || q < g.nvalid) sm.tl[g.own(q)] = V[q];
+            if (RAG ? q < g.nvalid : (q < NGW || q >= CPT - NGW)) sm.tl[g.own(q)] = V[q];
     }
     if (g.gk >= 0) sm.tl[g.gpos] = gv;
     __syncthreads();
