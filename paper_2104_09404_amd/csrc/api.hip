@@ -192,8 +192,8 @@ int tiles_for(int nx, const KernelCfg& c)
 // cells, 16 waves) when nx is even; odd lines take 2048-cell tiles of 4 cells
 // per thread and 8 waves, whose ragged variant the compiler holds free of
 // register spills.
-// Longest split line: 256 tiles of 4096 cells (one per compute unit), or 512
-// tiles of 2048 cells.
+// Longest split line: 2^20 cells (128 tiles of 8192 cells, or 256 of 4096);
+// lines of 2 cells per thread up to 2^19 cells (256 tiles of 2048).
 const int kMaxTiledLine = 1 << 20;
 const int kWideTileLine = 32768;
 
@@ -1949,6 +1949,18 @@ int plan_batch(const mgrit_problem* probs, int32_t count, const mgrit_params* p,
                 bk->offset.push_back(bk->nblocks);
                 bk->probs.push_back(i);
                 bk->nblocks += r.a.nchunks;
+            }
+            // serial solves of split lines (one work item per problem): line group
+            // g runs items g, g + groups, ... one after the other, so with the
+            // longest solves first the groups that run a second solve get short ones
+            for (BatchBucket& b : P.buckets) {
+                if (b.tiles == 0 || b.nblocks != (int)b.probs.size()) continue;
+                bool serial_all = true;
+                for (int i : b.probs)
+                    serial_all = serial_all && rec[i][ph].a.nchunks == 1 && rec[i][ph].a.end_mode == mgk::END_NONE;
+                if (serial_all)
+                    std::stable_sort(b.probs.begin(), b.probs.end(),
+                                     [&](int x, int y) { return rec[x][ph].a.nsteps > rec[y][ph].a.nsteps; });
             }
             for (BatchBucket& b : P.buckets) {
                 b.dev_off = sizeof(int) * bp->host_ints.size();
