@@ -20,7 +20,9 @@
  *     into tiles of balanced length, one workgroup per tile, which exchange
  *     alpha_LF and their edge fluxes once per Runge-Kutta stage through
  *     device memory; their launches are
- *     cooperative (all workgroups of a line resident at once).  Results are
+ *     cooperative (all workgroups of a line resident at once).  The tile
+ *     shape follows the line length (mgrit_tiled_config) and, for launches
+ *     of few chunks, the launch (mgrit_tiled_launch_config).  Results are
  *     bitwise the same as with one workgroup per line.  Split-line calls
  *     outside mgrit_cycle that overlap in time on one device (different
  *     streams or threads) share that device's synchronisation buffer and must
