@@ -30,6 +30,7 @@
 // error and every workgroup leaves.
 #pragma once
 #include <algorithm>
+#include <climits>
 
 #include "sweep_impl.h"
 
@@ -1139,10 +1140,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MGK_TIL
 // ---------------------------------------------------------------------------
 // Work items are the (problem, chunk) pairs of the launch's table, problem i
 // owning items offset[i] .. offset[i+1] - 1.  Line group grp (workgroups
-// grp G .. grp G + G - 1) takes items grp, grp + groups, ...  Each item runs
+// grp G .. grp G + G - 1) takes items grp, grp + groups, ..., or, with one
+// item per problem, the items a greedy schedule gives it (up to
+// kBatchSchedGroups groups and kBatchSchedItems items).  Each item runs
 // exactly tiled_chunk on its problem's arguments, with the problem's own
 // tile geometry; the group's slot ring simply continues from item to item.
 // A problem whose stop flag is set (it converged) contributes no work.
+constexpr int kBatchSchedGroups = 256;
+constexpr int kBatchSchedItems = 1024;
+
 template <int CPT, int NW, int K, int ST, bool RAG, int END, bool ROE>
 __device__ __forceinline__ void tiled_batch_body(const BatchLaunch& t)
 {
@@ -1160,7 +1166,47 @@ __device__ __forceinline__ void tiled_batch_body(const BatchLaunch& t)
     ts.G = G;
     ts.tile = tile;
     ts.ep = 0;
-    for (int j = grp; j < t.nblocks; j += t.groups) {
+    // One work item per problem (serial solves, listed longest first) and more
+    // items than line groups: the items go to the groups by the greedy rule
+    // (each to the group with the fewest steps so far, ties to the lowest
+    // group), which every workgroup evaluates identically; otherwise group g
+    // takes items g, g + groups, ...
+    __shared__ int owner[kBatchSchedItems];
+    const bool sched = t.nblocks == t.nprob && t.groups < t.nblocks && t.groups <= kBatchSchedGroups &&
+                       t.nblocks <= kBatchSchedItems;
+    if (sched) {
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            long long load[kBatchSchedGroups / 64];
+#pragma unroll
+            for (int r = 0; r < kBatchSchedGroups / 64; ++r) load[r] = (lane + 64 * r < t.groups) ? 0 : LLONG_MAX;
+            for (int j = 0; j < t.nblocks; ++j) {
+                long long best = LLONG_MAX;
+                int bg = 0;
+#pragma unroll
+                for (int r = 0; r < kBatchSchedGroups / 64; ++r)
+                    if (load[r] < best) {
+                        best = load[r];
+                        bg = lane + 64 * r;
+                    }
+                // lowest (load, group) over the wave
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const long long ob = __shfl_xor(best, off);
+                    const int og = __shfl_xor(bg, off);
+                    if (ob < best || (ob == best && og < bg)) {
+                        best = ob;
+                        bg = og;
+                    }
+                }
+                if (lane == (bg & 63)) load[bg >> 6] += t.args[t.problem[j]].nsteps;
+                if (lane == 0) owner[j] = bg;
+            }
+        }
+        __syncthreads();
+    }
+    for (int j = sched ? 0 : grp; j < t.nblocks; j += sched ? 1 : t.groups) {
+        if (sched && owner[j] != grp) continue;
         int lo = 0, hi = t.nprob - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
