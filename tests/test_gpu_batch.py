@@ -215,3 +215,33 @@ def test_batch_wide_lines(gpu, storage, levels, relax, cycle):
         assert same(ub[i], us), (i, prob[0].nx)
         assert ib[i] == n == 3
         assert close_hist(hb[i], hs), (i, hb[i], hs)
+
+
+def test_batch_scheduled_serial_solves(gpu):
+    """72 problems of 4098..4240 cells (split lines) with uneven step counts:
+    their serial coarse solves share one persistent launch of 4 tiles per
+    problem, one 1024-thread workgroup per compute unit, so 256 compute units
+    hold 64 line groups and the 72 solves go to the groups by the greedy
+    longest-first schedule.  Every iterate bitwise equal to the problem's
+    own solve."""
+    import torch
+
+    m, n = 8, 72
+    assert torch.cuda.get_device_properties(0).multi_processor_count // 4 < n
+    g = np.random.default_rng(91)
+    probs = []
+    for i in range(n):
+        nx = 4098 + 2 * i
+        flux = i % 2
+        a = float(g.uniform(0.5, 1.5)) if flux == 1 else 1.0
+        u0 = W.random_lines(9100 + i, 1, nx)[0]
+        speed = np.max(np.abs(u0)) if flux == 0 else a
+        nt = m * (4 + (7 * i) % 13)
+        probs.append((gpu.scheme(nx, flux=flux, a=a), nt, 0.6 / nx / speed, u0))
+    p = gpu.params(0, 0.0, m, 2, relax=1, max_iter=2, tol=-1.0, storage=0, sync_every=2)
+    ub, hb, ib, sb = run_batch(gpu, probs, p)
+    for i, prob in enumerate(probs):
+        us, hs, k, rc = run_single(gpu, prob, p)
+        assert same(ub[i], us), (i, prob[0].nx)
+        assert ib[i] == k == 2
+        assert close_hist(hb[i], hs), (i, hb[i], hs)
