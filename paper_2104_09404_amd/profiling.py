@@ -26,6 +26,11 @@
         (mgrit_relax on 65537 nodes, m = 16) under every compiled
         one-workgroup shape that covers 256 cells (SHORT_SHAPES), with
         HIP-event times per sweep.
+    python -m paper_2104_09404_amd.profiling serial [reps]
+        serial time stepping of the 65536-cell workload (workloads.
+        w2_burgers_weno5_large: N_T = 16384 steps of Phi on one line,
+        mgrit_serial), `reps` times after one warm-up, each timed with HIP
+        events on the launch stream; the launch's tile shape is printed.
     python -m paper_2104_09404_amd.profiling batch [cycles]
         the 512-problem batch (workloads.w3_batched, 2-level FCF, m = 8,
         C-point storage): one warm-up call of one cycle, then one
@@ -213,6 +218,30 @@ def shortlines(reps: int = 5, quiet: bool = False) -> dict:
     return out
 
 
+def serial(reps: int = 2):
+    import torch
+
+    from . import mgrit
+    from . import workloads as W
+
+    pb = W.w2_burgers_weno5_large()
+    s = mgrit.scheme_from_problem(pb)
+    u0 = torch.from_numpy(pb.u0).cuda()
+    out = torch.empty((pb.nt + 1, pb.nx), dtype=torch.float64, device="cuda")
+    print("serial stepping, N_x = %d, N_T = %d: tiles (cells per thread, waves, tiles) = %s"
+          % (pb.nx, pb.nt, mgrit.tiled_launch_config(pb.nx, 1)), flush=True)
+    mgrit.serial(s, pb.dt, pb.nt, u0, out)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mgrit.serial(s, pb.dt, pb.nt, u0, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        print("  %.2f ms, %.3f us per Runge-Kutta stage" % (ms, 1e3 * ms / (3 * pb.nt)), flush=True)
+
+
 def batch(cycles: int = 2):
     import time
 
@@ -255,6 +284,8 @@ if __name__ == "__main__":
         cycle1024(int(sys.argv[2]) if len(sys.argv) > 2 else 3)
     elif what == "shortlines":
         shortlines(int(sys.argv[2]) if len(sys.argv) > 2 else 5)
+    elif what == "serial":
+        serial(int(sys.argv[2]) if len(sys.argv) > 2 else 2)
     elif what == "batch":
         batch(int(sys.argv[2]) if len(sys.argv) > 2 else 2)
     else:
