@@ -167,7 +167,9 @@ def time_to_tolerance(mgrit):
       * the 1024-cell WENO5 problem with a step that puts the coarsest level at
         CFL 0.8 (m = 4, 3 levels, 4096 steps);
       * the 4096-cell adjoint problem likewise (m = 4, 3 levels, 2048 steps,
-        coarsest CFL 0.8).
+        coarsest CFL 0.8);
+      * the 65536-cell problem with the benchmark's N_T = 16384 and m = 16, 3
+        levels and a step that puts the coarsest level at CFL 0.8.
     The 1024- and 65536-cell benchmark problems themselves have coarse CFL
     51 and 3277 and diverge, as sec 4 finds for large coarse CFL."""
     import torch
@@ -176,7 +178,7 @@ def time_to_tolerance(mgrit):
 
     out = {}
     probs = [W.w0_burgers_k0(), W.e4_high_order(2, 0), W.e1_fine_matching(cycle=0), W.e1_fine_matching(cycle=1),
-             W.w1_stable_coarse(), W.w4_stable_coarse()]
+             W.w1_stable_coarse(), W.w4_stable_coarse(), W.w2_stable_coarse()]
     for pb in probs:
         s = mgrit.scheme_from_problem(pb)
         u0 = torch.from_numpy(pb.u0).cuda()

@@ -262,6 +262,19 @@ def w1_stable_coarse(nx: int = 1024, nt: int = 4096, m: int = 4, levels: int = 3
                    levels, 1, pb.u0, max_iter=nt // m, cfl=cfl0)
 
 
+def w2_stable_coarse(nx: int = 65536, nt: int = 16384, m: int = 16, levels: int = 3,
+                     coarse_cfl: float = 0.8) -> Problem:
+    """The 65536-cell problem (u0 of w2_burgers_weno5_large, N_T and m of the
+    benchmark) with 3 levels and a step that puts the coarsest level at CFL
+    ``coarse_cfl`` (level 0 at coarse_cfl / m^(levels-1)), so that MGRIT
+    converges."""
+    pb = w2_burgers_weno5_large(nx=nx, nt=nt, m=m, levels=levels)
+    cfl0 = coarse_cfl / float(m ** (levels - 1))
+    dt = dt_for_cfl(cfl0, 1.0 / nx, float(np.max(np.abs(pb.u0))))
+    return Problem("burgers_weno5_nx%d_coarse_cfl%.1f" % (nx, coarse_cfl), FLUX_BURGERS, 2, 3, nx, nt, dt, m,
+                   levels, 1, pb.u0, max_iter=nt // m, cfl=cfl0)
+
+
 def w4_stable_coarse(coarse_cfl: float = 0.8) -> Problem:
     """The adjoint workload's problem (4096 cells, 2048 steps, u0 and u_target
     of w4_adjoint) with m = 4 and 3 levels and a step that puts the coarsest

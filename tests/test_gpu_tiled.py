@@ -366,3 +366,27 @@ def test_w2_full_size_sampled(orc, gpu):
     assert checked >= 2
     del ug
     torch.cuda.empty_cache()
+
+
+def test_w2_stable_coarse_converges_to_serial(orc, gpu):
+    """The 65536-cell problem with the benchmark's N_T = 16384 and m = 16, on
+    3 levels with a step that puts the coarsest level at CFL 0.8: FCF
+    V-cycles reach a residual of 1e-10 within 4 cycles, and the iterate equals
+    serial stepping of the same problem (MGRIT's fixed point) to round-off;
+    the first steps of both equal the oracle's serial stepping."""
+    import torch
+
+    pb = W.w2_stable_coarse()
+    sg = gpu.scheme_from_problem(pb)
+    p = gpu.params(pb.nt, pb.dt, pb.m, pb.levels, relax=1, max_iter=8, tol=1e-10)
+    ug = torch.zeros((pb.nt + 1, pb.nx), dtype=torch.float64, device="cuda")
+    rc, hist, n = gpu.cycle(sg, p, T(pb.u0), ug)
+    assert rc == 0 and n <= 4 and hist[-1] <= 1e-10, (rc, n, hist)
+    traj = torch.empty_like(ug)
+    gpu.serial(sg, pb.dt, pb.nt, T(pb.u0), traj)
+    diff = float((ug - traj).abs().max())
+    assert diff < 1e-11 * float(traj.abs().max()), diff
+    us = orc.serial(orc.scheme(pb.nx), pb.dt, 2 * pb.m, pb.u0)
+    assert np.all(rel_lines(H(ug[: 2 * pb.m + 1]), us) < TOL)
+    del ug, traj
+    torch.cuda.empty_cache()
