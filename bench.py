@@ -23,7 +23,10 @@ level-0 F + C sweep); its average duration gives the roofline figure.
 Extra fields: the same measurement on the 1024-cell problem, the 512-problem
 batch, the adjoint/forward ratio against a serial and an MGRIT forward, MGRIT
 wall time to a residual of 1e-10 where MGRIT converges (with GPU serial
-stepping beside it), and the scheme-variant and system sweeps.
+stepping beside it), and the scheme-variant and system sweeps.  Beside the
+CPU baseline's Phi rate: the oracle's MGRIT on the host (one iteration of
+the 1024-cell problem, the 64-cell first-order problem to 1e-10, and one
+iteration of the benchmark problem extrapolated from the Phi rate).
 """
 from __future__ import annotations
 
@@ -257,6 +260,47 @@ def cpu_baseline(pb, budget_s):
             "sample": "%d Phi steps (WENO5 + LF + SSPRK3) of 2 lines x %d cells of the benchmark problem, "
                       "%.1f s on 1 thread" % (reps, pb.nx, el),
             "build": flags, "host_cpu": model, "host_nproc": ncpu, "host_cpus_usable": usable}
+
+
+def cpu_mgrit(phi_rate, gpu):
+    """The oracle's FAS-MGRIT on the host in the same speed build as
+    cpu_baseline: one iteration (V-cycle plus the residual of its result) of
+    the 1024-cell problem, and the first-order 64-cell problem to a residual
+    of 1e-10.  A CPU iteration of the 65536-cell benchmark problem (about
+    five minutes) is not run: it is extrapolated from the measured Phi rate and
+    the cell steps of one GPU iteration, and labelled so.  ``gpu`` holds the
+    GPU figures of the same problems where the run measured them."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle
+    from paper_2104_09404_amd import workloads as W
+
+    def run(pb, max_iter, tol):
+        so = oracle.scheme(pb.nx, flux=pb.flux, k=pb.k, stepper=pb.stepper, a=pb.a, eps=pb.eps, L=pb.L)
+        po = oracle.params(pb.nt, pb.dt, pb.m, pb.levels, relax=pb.relax, max_iter=max_iter, tol=tol)
+        return oracle.timing_mgrit(so, po, pb.u0)
+
+    out = {}
+    pb = W.w1_burgers_weno5()
+    el, n, res, _ = run(pb, 1, -1.0)
+    rec = {"workload": pb.name, "s_per_iteration": el, "iterations": n, "threads": 1}
+    if gpu.get("nx1024_ms_per_step"):
+        rec["gpu_ms_per_iteration"] = gpu["nx1024_ms_per_step"]
+        rec["cpu_over_gpu"] = el * 1e3 / gpu["nx1024_ms_per_step"]
+    out["burgers_weno5_nx1024_one_iteration"] = rec
+    pb = W.w0_burgers_k0()
+    el, n, res, _ = run(pb, pb.max_iter, 1e-10)
+    rec = {"workload": pb.name, "s": el, "cycles": n, "residual": res, "threads": 1}
+    if gpu.get("k0_ms_to_tol"):
+        rec["gpu_ms"] = gpu["k0_ms_to_tol"]
+    out["burgers_k0_fe_nx64_to_1e-10"] = rec
+    if gpu.get("cell_steps_per_step"):
+        out["burgers_weno5_nx65536_one_iteration"] = {
+            "s_per_iteration_extrapolated": gpu["cell_steps_per_step"] / phi_rate,
+            "basis": "extrapolated, not run: cell steps of one GPU iteration (%.4g) / the oracle's measured "
+                     "Phi rate on this problem's lines" % gpu["cell_steps_per_step"],
+            "gpu_ms_per_iteration": gpu.get("ms_per_step"),
+        }
+    return out
 
 
 def run_cycles(mgrit, pb, steps, warmup, dominant="relax_fc_l0", storage=0):
@@ -573,6 +617,13 @@ def main():
         out["systems"] = None if args.no_variants else system_rates()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb, args.cpu_seconds)
+        gpu = {"cell_steps_per_step": r["cell_steps"] / args.steps, "ms_per_step": r["ms_per_step"]}
+        if isinstance(out.get("burgers_weno5_nx1024"), dict):
+            gpu["nx1024_ms_per_step"] = out["burgers_weno5_nx1024"]["ms_per_step"]
+        ttt = out.get("time_to_tolerance")
+        if isinstance(ttt, dict) and isinstance(ttt.get("burgers_k0_fe_nx64"), dict):
+            gpu["k0_ms_to_tol"] = ttt["burgers_k0_fe_nx64"]["ms"]
+        out["cpu_baseline"]["mgrit"] = cpu_mgrit(out["cpu_baseline"]["value"], gpu)
     print(json.dumps(out))
 
 

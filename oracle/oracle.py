@@ -6,9 +6,9 @@ leg of the benchmark import this module.  The product library never does.
 The shared object is compiled with gcc (``-O2 -ffp-contract=off``, no
 fast-math) into ``oracle/_build/``; :func:`build` always recompiles,
 :func:`lib` compiles only when nothing is built yet.  :func:`timing_phi`
-times the same source built for speed (``-O3 -march=native``, still no
-fast-math) on the machine it runs on; only the CPU baseline of the benchmark
-uses that build.
+and :func:`timing_mgrit` time the same source built for speed (``-O3
+-march=native``, still no fast-math) on the machine they run on; only the
+CPU baseline of the benchmark uses that build.
 """
 from __future__ import annotations
 
@@ -120,20 +120,54 @@ def lib():
 TIMING_FLAGS = ["-O3", "-march=native", "-fno-fast-math", "-std=c99", "-fPIC", "-shared"]
 
 
-def timing_phi(s: Scheme, dt: float, lines: np.ndarray, budget_s: float):
-    """Apply Phi to every row of ``lines`` repeatedly, for about ``budget_s``
-    seconds, with the oracle source built for speed in a temporary directory
-    (flags TIMING_FLAGS, on the host that runs this).  Returns (repetitions,
-    seconds, compiler flags)."""
-    import tempfile
+_timing_lib = None
+
+
+def timing_lib():
+    """The oracle source built for speed (flags TIMING_FLAGS, on the host that
+    runs this) in a temporary directory, once per process.  Only the timing
+    entry points are declared; parity uses lib()."""
+    global _timing_lib
+    if _timing_lib is None:
+        import tempfile
+
+        tmp = tempfile.mkdtemp(prefix="oracle_timing_")
+        so = os.path.join(tmp, "libmgrit_oracle_timing.so")
+        subprocess.run(["gcc"] + TIMING_FLAGS + ["-o", so, SRC, "-lm"], check=True)
+        L = C.CDLL(so)
+        dp = C.POINTER(C.c_double)
+        L.orc_phi_lines.argtypes = [C.POINTER(Scheme), C.c_double, dp, dp, C.c_int64]
+        L.orc_mgrit.argtypes = [C.POINTER(Scheme), C.POINTER(Params), dp, dp, dp, C.POINTER(C.c_int32)]
+        L.orc_mgrit.restype = C.c_int
+        _timing_lib = L
+    return _timing_lib
+
+
+def timing_mgrit(s: Scheme, p: Params, u0):
+    """One call of the oracle's FAS-MGRIT (the same algorithm as mgrit()) in
+    the build of timing_lib(), from the zero initial iterate.  Returns
+    (seconds, cycles applied, last residual norm, compiler flags)."""
     import time
 
-    tmp = tempfile.mkdtemp(prefix="oracle_timing_")
-    so = os.path.join(tmp, "libmgrit_oracle_timing.so")
-    subprocess.run(["gcc"] + TIMING_FLAGS + ["-o", so, SRC, "-lm"], check=True)
-    L = C.CDLL(so)
-    L.orc_phi_lines.argtypes = [C.POINTER(Scheme), C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                C.c_int64]
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    u = np.zeros((p.nt + 1, line_len(s)))
+    hist = np.full(p.max_iter + 1, np.nan)
+    iters = C.c_int32(0)
+    L = timing_lib()
+    t0 = time.perf_counter()
+    L.orc_mgrit(C.byref(s), C.byref(p), _p(u0), _p(u), _p(hist), C.byref(iters))
+    el = time.perf_counter() - t0
+    n = iters.value
+    return el, n, float(hist[n]) if p.levels > 1 else float("nan"), " ".join(["gcc"] + TIMING_FLAGS)
+
+
+def timing_phi(s: Scheme, dt: float, lines: np.ndarray, budget_s: float):
+    """Apply Phi to every row of ``lines`` repeatedly, for about ``budget_s``
+    seconds, in the build of timing_lib().  Returns (repetitions, seconds,
+    compiler flags)."""
+    import time
+
+    L = timing_lib()
     a = np.ascontiguousarray(lines, dtype=np.float64)
     b = np.zeros_like(a)
     nlines = a.size // line_len(s)
