@@ -200,7 +200,8 @@ def time_to_tolerance(mgrit):
         name = pb.name + ("_fcycle" if pb.cycle == 1 else "")
         out[name] = {"ms": ms, "cycles": n, "converged": rc == 0, "residual": hist[-1], "gpu_serial_ms": ser,
                      "mgrit_over_serial": ms / ser, "nx": pb.nx, "nt": pb.nt, "m": pb.m, "levels": pb.levels,
-                     "coarsest_cfl": pb.cfl * pb.m ** (pb.levels - 1)}
+                     "coarsest_cfl": pb.cfl * pb.m ** (pb.levels - 1),
+                     "cfl_per_level": [pb.cfl * pb.m ** lv for lv in range(pb.levels)]}
         del u, ws
     out["verdict"] = ("MGRIT faster than GPU serial stepping on: " +
                       ", ".join(k for k, v in out.items() if v["converged"] and v["ms"] < v["gpu_serial_ms"])
