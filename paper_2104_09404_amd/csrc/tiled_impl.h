@@ -724,6 +724,13 @@ __device__ __forceinline__ bool level_step_t(double (&x)[CPT], double& gx, doubl
     return phi_t<CPT, NW, K, ST, RAG, ROE>(x, gx, dt, g, sm, pc, ts);
 }
 
+// A whole thread's cells at a 16-byte aligned address move as pairs.
+template <int CPT>
+__device__ __forceinline__ bool t_pairs(const double* p, int nvalid)
+{
+    return CPT % 2 == 0 && nvalid == CPT && (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+}
+
 // line access restricted to the tile's own cells (and the thread's ghost cell)
 template <int CPT, int NW>
 __device__ __forceinline__ void t_load(double (&x)[CPT], double& gx, const double* src, const TGeo<CPT, NW>& g)
@@ -733,12 +740,28 @@ __device__ __forceinline__ void t_load(double (&x)[CPT], double& gx, const doubl
     gx = (g.gk >= 0) ? src[g.gcell] : 0.0;
 }
 
+// Stores of whole threads go out as 16-byte pairs where aligned: thread t's
+// cells lie 8 CPT bytes from its neighbour's, so each store instruction of a
+// wave touches 64 cache lines, and pairs halve the requests per line
+// written.  (Loads stay single: as pairs, their registers made the sweep
+// kernels spill more.)
 template <int CPT, int NW>
 __device__ __forceinline__ void t_store(const double (&x)[CPT], double* dst, const TGeo<CPT, NW>& g)
 {
+    double* p = dst + g.x0 + g.j0;
+    if (t_pairs<CPT>(p, g.nvalid)) {
+#pragma unroll
+        for (int q = 0; q + 1 < CPT; q += 2) {
+            double2 v;
+            v.x = x[q];
+            v.y = x[q + 1];
+            *reinterpret_cast<double2*>(p + q) = v;
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < CPT; ++q)
-        if (q < g.nvalid) dst[g.x0 + g.j0 + q] = x[q];
+        if (q < g.nvalid) p[q] = x[q];
 }
 
 // x += the tile's cells of line src (and the ghost): every load is issued
@@ -771,9 +794,17 @@ __device__ __forceinline__ void t_add(double (&x)[CPT], double& gx, const double
 template <int CPT, int NW>
 __device__ __forceinline__ void t_copy(const double* src, double* dst, const TGeo<CPT, NW>& g)
 {
+    const double* a = src + g.x0 + g.j0;
+    double* b = dst + g.x0 + g.j0;
+    if (t_pairs<CPT>(a, g.nvalid) && t_pairs<CPT>(b, g.nvalid)) {
+#pragma unroll
+        for (int q = 0; q + 1 < CPT; q += 2)
+            *reinterpret_cast<double2*>(b + q) = *reinterpret_cast<const double2*>(a + q);
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < CPT; ++q)
-        if (q < g.nvalid) dst[g.x0 + g.j0 + q] = src[g.x0 + g.j0 + q];
+        if (q < g.nvalid) b[q] = a[q];
 }
 
 // sum over the tile of (a - b)^2 in a fixed order; valid in thread 0
